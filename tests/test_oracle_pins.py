@@ -1,0 +1,457 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no implementation to compare with).
+
+Each test names the passage of the paper it pins.  The paper prints no worked numerical example for the
+hot path, so the pins are library routines, closed forms, invariants, brute force and a manufactured
+solution; each is chosen so that a plausible slip (dropped term, sign, index, transposed operand) fails.
+"""
+import math
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from paper_1806_11456_amd import inputs as I
+from tests import mms
+
+LG, LGL = I.FAMILY_LG, I.FAMILY_LGL
+
+
+# ------------------------------------------------------------------------------------------------------
+# Sec. 2, nodal tensor-product basis on Gauss (and Gauss-Lobatto) nodes
+# ------------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("N", range(0, 16))
+def test_gauss_nodes_match_numpy(oracle_mod, N):
+    x, w, D, lm, lp = oracle_mod.basis(N, LG)
+    xr, wr = np.polynomial.legendre.leggauss(N + 1)
+    assert np.abs(x - xr).max() < 2e-15
+    assert np.abs(w - wr).max() < 2e-15 * max(1.0, wr.max())
+
+
+@pytest.mark.parametrize("N", range(1, 16))
+def test_lobatto_nodes_and_exactness(oracle_mod, N):
+    x, w, D, lm, lp = oracle_mod.basis(N, LGL)
+    inner = np.sort(np.polynomial.legendre.Legendre.basis(N).deriv().roots().real) if N > 1 else np.zeros(0)
+    assert np.abs(x[1:-1] - inner).max(initial=0.0) < 1e-14
+    assert x[0] == -1.0 and x[-1] == 1.0
+    for k in range(0, 2 * N):  # exact to degree 2N-1
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.dot(w, x ** k) - exact) < 1e-13
+
+
+@pytest.mark.parametrize("family", [LG, LGL])
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 7, 9, 12])
+def test_quadrature_derivative_boundary(oracle_mod, family, N):
+    x, w, D, lm, lp = oracle_mod.basis(N, family)
+    top = 2 * N + 1 if family == LG else 2 * N - 1
+    for k in range(top + 1):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs(np.dot(w, x ** k) - exact) < 1e-13
+    assert abs(w.sum() - 2.0) < 1e-14
+    for k in range(N + 1):  # D x^k = k x^(k-1)
+        dk = k * x ** (k - 1) if k else np.zeros_like(x)
+        assert np.abs(D @ x ** k - dk).max() < 1e-11 * max(1, N) ** 2
+        assert abs(lp @ x ** k - 1.0) < 1e-12 and abs(lm @ x ** k - (-1.0) ** k) < 1e-12
+
+
+# ------------------------------------------------------------------------------------------------------
+# Sec. 3.1: restriction = L2 projection to the lower order; prolongation = interpolation
+# ------------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("family", [LG, LGL])
+def test_prolong_then_restrict_identity(oracle_mod, family):
+    for p in range(2, 16):
+        for n in range(1, p):
+            R = oracle_mod.projection(n, p, family)
+            P = oracle_mod.interpolation(n, p, family)
+            assert np.abs(R @ P - np.eye(n + 1)).max() < 2e-13, (n, p)
+            PR = P @ R
+            assert np.abs(PR @ PR - PR).max() < 2e-13
+
+
+@pytest.mark.parametrize("family", [LG, LGL])
+def test_restriction_is_continuous_l2_projection(oracle_mod, family):
+    rng = np.random.default_rng(7)
+    xq, wq = np.polynomial.legendre.leggauss(64)
+    for p, n in ((5, 2), (7, 3), (9, 8), (4, 1)):
+        xf = oracle_mod.basis(p, family)[0]
+        xc = oracle_mod.basis(n, family)[0]
+        f = rng.standard_normal(p + 1)  # a degree-p polynomial through the fine nodes
+        poly = np.polynomial.polynomial.Polynomial.fit(xf, f, p)
+        fq = poly(xq)
+        # brute force: Legendre coefficients of the projection onto P_n
+        coef = [(2 * k + 1) / 2.0 * np.sum(wq * fq * np.polynomial.legendre.Legendre.basis(k)(xq)) for k in range(n + 1)]
+        proj = np.polynomial.legendre.Legendre(coef)(xc)
+        R = oracle_mod.projection(n, p, family)
+        assert np.abs(R @ f - proj).max() < 1e-12 * max(1.0, np.abs(f).max())
+
+
+# ------------------------------------------------------------------------------------------------------
+# Sec. 2: metric terms (covariant / contravariant, invariant curl form, J)
+# ------------------------------------------------------------------------------------------------------
+def test_affine_metrics_closed_form(oracle_mod):
+    mesh = I.box_mesh((2, 3, 2), (0, 0, 0), (1.0, 0.6, 2.0), M=(1, 1, 1), periodic=(False,) * 3)
+    orders = I.random_orders(mesh.K, 1, 5, 3)
+    X, Ja, J, Nout = oracle_mod.Oracle(mesh, I.Physics()).geometry(orders)
+    h = np.array([0.5, 0.2, 1.0])
+    assert np.abs(J - h.prod() / 8).max() < 1e-15
+    for i in range(3):
+        exp = np.zeros(3)
+        exp[i] = h.prod() / 8 * 2.0 / h[i]  # J * dxi_i/dx_i
+        assert np.abs(Ja[i] - exp[:, None]).max() < 1e-13
+
+
+def _metric_identity_residual(O, mesh, orders, family):
+    X, Ja, J, _ = O.Oracle(mesh, I.Physics(family=family)).geometry(orders)
+    off = I.node_offsets(orders)
+    worst = 0.0
+    for e in range(mesh.K):
+        n = orders[e] + 1
+        Ds = [O.basis(int(orders[e][d]), family)[2] for d in range(3)]
+        for comp in range(3):
+            tot = np.zeros((n[2], n[1], n[0]))
+            for i in range(3):
+                f = Ja[i, comp, off[e]:off[e + 1]].reshape(n[2], n[1], n[0])
+                ax = 2 - i
+                tot += np.moveaxis(np.tensordot(Ds[i], np.moveaxis(f, ax, 0), axes=(1, 0)), 0, ax)
+            worst = max(worst, np.abs(tot).max())
+    return worst, np.abs(Ja).max()
+
+
+@pytest.mark.parametrize("family", [LG, LGL])
+def test_discrete_metric_identity_curved(oracle_mod, family):
+    mesh = I.box_mesh((2, 2, 2), (-1, -1, -1), (1, 1, 1), M=(3, 3, 3), wobble=0.2)
+    orders = I.random_orders(mesh.K, 1, 6, 5)
+    worst, scale = _metric_identity_residual(oracle_mod, mesh, orders, family)
+    assert worst < 1e-13 * scale * 50
+
+
+def test_jacobian_positive_on_workload_meshes(oracle_mod):
+    for mesh, orders in ((I.plate_mesh(8, 4), I.uniform_orders(32, (6, 6, 1))),
+                         (I.ogrid_mesh(2, 2), I.random_orders(48, 1, 7, 3))):
+        J = oracle_mod.Oracle(mesh, I.Physics()).geometry(orders)[2]
+        assert J.min() > 0
+
+
+# ------------------------------------------------------------------------------------------------------
+# Sec. 2 (free-stream preservation of the curl form) and conservation of the weak form
+# ------------------------------------------------------------------------------------------------------
+def _fs_residual(O, mesh, orders, family, mach=0.3):
+    ph = I.Physics(mach=mach, reynolds=100.0, family=family)
+    nn = int(I.node_offsets(orders)[-1])
+    Q = I.freestream_state(nn, mach)
+    R = O.Oracle(mesh, ph).residual(orders, Q)
+    # scale: the size of one volume-term contribution of the divergence, |F| / (J w) ~ p_inf N^2 / h
+    return np.abs(R).max()
+
+
+@pytest.mark.parametrize("M", [1, 2])
+def test_free_stream_preserved_lobatto_any_order(oracle_mod, M):
+    mesh = I.box_mesh((3, 3, 3), (-1, -1, -1), (1, 1, 1), M=(M, M, M), wobble=0.15)
+    for N in (1, 2, 3, 5):
+        assert _fs_residual(oracle_mod, mesh, I.uniform_orders(mesh.K, (N, N, N)), LGL) < 1e-9
+
+
+def test_free_stream_gauss_needs_twice_mapping_order(oracle_mod):
+    mesh = I.box_mesh((3, 3, 3), (-1, -1, -1), (1, 1, 1), M=(2, 2, 2), wobble=0.15)
+    for N in (4, 5):
+        assert _fs_residual(oracle_mod, mesh, I.uniform_orders(mesh.K, (N, N, N)), LG) < 1e-8
+    # documented failure below 2M: extrapolated Gauss traces of the metric do not match across faces
+    for N in (2, 3):
+        assert _fs_residual(oracle_mod, mesh, I.uniform_orders(mesh.K, (N, N, N)), LG) > 1e-3
+
+
+def test_free_stream_nonconforming_rotated(oracle_mod):
+    base = I.box_mesh((3, 3, 3), (-1, -1, -1), (1, 1, 1), M=(2, 2, 2), wobble=0.15)
+    mesh, orders = I.reorient(base, 11, period=(2, 2, 2), orders=I.random_orders(base.K, 4, 6, 2))
+    assert (mesh.orient != 0).any()
+    assert _fs_residual(oracle_mod, mesh, orders, LG) < 2e-8
+
+
+@pytest.mark.parametrize("family", [LG, LGL])
+def test_discrete_conservation_periodic(oracle_mod, family):
+    base = I.box_mesh((3, 3, 3), (-1, -1, -1), (1, 1, 1), M=(2, 2, 2), wobble=0.15)
+    mesh, orders = I.reorient(base, 3, period=(2, 2, 2), orders=I.random_orders(base.K, 1, 5, 1))
+    ph = I.Physics(mach=0.3, reynolds=50.0, family=family)
+    o = oracle_mod.Oracle(mesh, ph)
+    nn = int(I.node_offsets(orders)[-1])
+    Q = I.perturbed_freestream(nn, 0.3, 0.05, 4)
+    A = o.operator(orders, Q)
+    J = o.geometry(orders)[2]
+    off = I.node_offsets(orders)
+    tot, mag = np.zeros(5), np.zeros(5)
+    for e in range(mesh.K):
+        ws = [oracle_mod.basis(int(orders[e][d]), family)[1] for d in range(3)]
+        W = np.einsum("k,j,i->kji", ws[2], ws[1], ws[0]).ravel()
+        s = slice(off[e], off[e + 1])
+        tot += (A[:, s] * J[s] * W).sum(axis=1)
+        mag += np.abs(A[:, s] * J[s] * W).sum(axis=1)
+    assert np.all(np.abs(tot) < 1e-12 * mag)
+
+
+# ------------------------------------------------------------------------------------------------------
+# Sec. 2: Roe advective Riemann solver
+# ------------------------------------------------------------------------------------------------------
+def _state(rho, u, v, w, p, g=1.4):
+    return np.array([rho, rho * u, rho * v, rho * w, p / (g - 1) + 0.5 * rho * (u * u + v * v + w * w)])
+
+
+def test_roe_consistency_antisymmetry_upwinding(oracle_mod):
+    ph = I.Physics(mach=0.5)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        a = _state(1 + 0.3 * rng.random(), *rng.standard_normal(3) * 0.4, 2 + rng.random())
+        b = _state(1 + 0.3 * rng.random(), *rng.standard_normal(3) * 0.4, 2 + rng.random())
+        Fa, _ = oracle_mod.fluxes(ph, a, np.zeros((4, 3)))
+        assert np.abs(oracle_mod.roe(ph, a, a, n) - Fa.T @ n).max() < 1e-13 * np.abs(Fa).max()
+        f1 = oracle_mod.roe(ph, a, b, n)
+        f2 = oracle_mod.roe(ph, b, a, -n)
+        assert np.abs(f1 + f2).max() < 1e-13 * np.abs(f1).max()
+    # supersonic along n: every wave speed has one sign, the Roe property makes the flux fully upwind
+    n = np.array([0.6, 0.8, 0.0])
+    a = _state(1.0, 3.0 * 0.6, 3.0 * 0.8, 0.1, 1.0)
+    b = _state(1.2, 2.7 * 0.6, 2.9 * 0.8, -0.1, 1.1)
+    Fa, _ = oracle_mod.fluxes(ph, a, np.zeros((4, 3)))
+    Fb, _ = oracle_mod.fluxes(ph, b, np.zeros((4, 3)))
+    assert np.abs(oracle_mod.roe(ph, a, b, n) - Fa.T @ n).max() < 1e-12 * np.abs(Fa).max()
+    assert np.abs(oracle_mod.roe(ph, a, b, -n) - Fb.T @ (-n)).max() < 1e-12 * np.abs(Fb).max()
+
+
+def test_viscous_flux_closed_form(oracle_mod):
+    """App. A: Stokes stress tensor, 1/Re scaling, heat-flux coefficient, Sutherland viscosity."""
+    ph = I.Physics(mach=0.3, reynolds=40.0)
+    q = _state(1.3, 0.4, -0.2, 0.1, 11.0)
+    rho, u = 1.3, np.array([0.4, -0.2, 0.1])
+    p = 11.0
+    T = 1.4 * 0.09 * p / rho
+    S = 110.4 / 288.15
+    mu = T ** 1.5 * (1 + S) / (T + S)
+    g = np.random.default_rng(1).standard_normal((4, 3))
+    _, Fv = oracle_mod.fluxes(ph, q, g)
+    gv = g[:3]
+    tau = mu * (gv + gv.T) - 2.0 / 3.0 * mu * np.trace(gv) * np.eye(3)
+    kap = mu / (0.4 * 0.72 * 0.09)
+    for c in range(3):
+        exp = np.array([0, *tau[c], u @ tau[c] + kap * g[3, c]]) / 40.0
+        assert np.abs(Fv[c] - exp).max() < 1e-14 * np.abs(exp).max()
+
+
+# ------------------------------------------------------------------------------------------------------
+# Sec. 3.1: Williamson low-storage RK3 smoother
+# ------------------------------------------------------------------------------------------------------
+def test_rk3_stability_polynomial(oracle_mod):
+    for z in (-0.1, -0.7, -1.9, -2.5, 0.3):
+        got = oracle_mod.rk3_linear(z, 1.0, 1.0)
+        assert abs(got - (1 + z + z * z / 2 + z ** 3 / 6)) < 1e-15
+
+
+# ------------------------------------------------------------------------------------------------------
+# BR1 gradient (Sec. 2 gradient in reference space)
+# ------------------------------------------------------------------------------------------------------
+def test_br1_gradient_constant_and_linear(oracle_mod):
+    mach = 0.3
+    mesh = I.box_mesh((2, 2, 2), (0, 0, 0), (1, 2, 1), M=(1, 1, 1), periodic=(True,) * 3)
+    # rho e carries 1/2 |v|^2, quadratic for a linear velocity: its face trace is exact from order 2 on
+    orders = I.random_orders(mesh.K, 2, 4, 9)
+    ph = I.Physics(mach=mach)
+    o = oracle_mod.Oracle(mesh, ph)
+    nn = int(I.node_offsets(orders)[-1])
+    g = o.gradient(orders, I.freestream_state(nn, mach))
+    assert np.abs(g).max() < 1e-11
+    # linear W on affine elements: the isolated (own-trace) gradient is exact
+    X = o.geometry(orders)[0]
+    x, y, z = X
+    u, v, w = 0.3 + 0.2 * x - 0.1 * y, -0.05 + 0.1 * z, 0.02 * x + 0.03 * y
+    p = 1.0 / (1.4 * mach ** 2) * (1 + 0.01 * x - 0.02 * z)
+    Q = I.conserved(np.ones(nn), u, v, w, p)
+    g = o.gradient(orders, Q, isolated=True)
+    pinf = 1.0 / (1.4 * mach ** 2)
+    exp = {(0, 0): 0.2, (0, 1): -0.1, (1, 2): 0.1, (2, 0): 0.02, (2, 1): 0.03,
+           (3, 0): 1.4 * mach ** 2 * pinf * 0.01, (3, 2): -1.4 * mach ** 2 * pinf * 0.02}
+    for k in range(4):
+        for c in range(3):
+            assert np.abs(g[k, c] - exp.get((k, c), 0.0)).max() < 1e-12, (k, c)
+
+
+# ------------------------------------------------------------------------------------------------------
+# Sec. 3.2.1: truncation error -- spectral convergence (manufactured solution) and exact zeros
+# ------------------------------------------------------------------------------------------------------
+def _mms_periodic():
+    x, y, z = sp.symbols("x y z")
+    pi = sp.pi
+    mach = 0.3
+    pinf = 1 / (1.4 * mach ** 2)
+    return mms.source_function(1 + 0.1 * sp.sin(pi * (x + y)), 1 + 0.1 * sp.sin(pi * z), 0.1 * sp.cos(pi * x),
+                               0.05 * sp.sin(pi * y), pinf * (1 + 0.05 * sp.cos(pi * (x - z))), mach, 50.0), mach
+
+
+@pytest.mark.parametrize("isolated", [False, True])
+def test_truncation_error_spectral_decay(oracle_mod, isolated):
+    (qf, sf), mach = _mms_periodic()
+    mesh = I.box_mesh((2, 2, 2), (0, 0, 0), (2, 2, 2), M=(1, 1, 1))
+    o = oracle_mod.Oracle(mesh, I.Physics(mach=mach, reynolds=50.0))
+    errs = []
+    for N in range(1, 11):
+        orders = I.uniform_orders(mesh.K, (N, N, N))
+        X = o.geometry(orders)[0]
+        errs.append(np.abs(o.residual(orders, qf(X), sf(X), isolated=isolated)).max())
+    errs = np.array(errs)
+    # exponential decay (it comes in odd/even pairs): linear-log slope, overall drop, drop every two orders
+    slope = np.polyfit(np.arange(1, 11), np.log(errs), 1)[0]
+    assert slope < -0.7, errs
+    assert errs[-1] < 2e-4 * errs[0], errs
+    assert np.all(errs[2:] < 0.7 * errs[:-2]), errs
+
+
+def test_tau_zero_for_uniform_state(oracle_mod):
+    mesh = I.box_mesh((2, 2, 2), (0, 0, 0), (1, 1, 1), M=(1, 1, 1), periodic=(True,) * 3)
+    orders = I.random_orders(mesh.K, 2, 4, 4)
+    ph = I.Physics(mach=0.2, reynolds=100.0)
+    o = oracle_mod.Oracle(mesh, ph)
+    Q = I.freestream_state(int(I.node_offsets(orders)[-1]), 0.2)
+    for iso in (0, 1):
+        tau, _ = o.tau_3v(orders, Q, isolated=iso, beta_pre=2, beta_post=2, beta_coarse=2)
+        assert np.nanmax(tau) < 1e-9
+
+
+def test_isolated_tau_directional_split(oracle_mod):
+    """rho = 1, p const, u = a + b x: the state is quadratic and the fluxes cubic in x only.  The isolated
+    estimate vanishes for directions 2, 3 at every order.  Along x the Gauss weak form integrates the cubic
+    flux exactly once the quadratic state is represented (N1 >= 2: quadrature exact to degree 2 N1 + 1, face
+    traces exact), and it is non-zero at N1 = 1."""
+    x, y, z = sp.symbols("x y z")
+    mach = 0.25
+    pinf = 1 / (1.4 * mach ** 2)
+    qf, sf = mms.source_function(sp.Integer(1), 0.4 + 0.3 * x, sp.Integer(0), sp.Integer(0), sp.Float(pinf), mach,
+                                 30.0)
+    mesh = I.box_mesh((2, 2, 2), (0, 0, 0), (1, 1, 1), M=(1, 1, 1), periodic=(False,) * 3)
+    orders = I.uniform_orders(mesh.K, (5, 4, 4))
+    o = oracle_mod.Oracle(mesh, I.Physics(mach=mach, reynolds=30.0))
+    X = o.geometry(orders)[0]
+    Q, S = qf(X), sf(X)
+    tau, Qout = o.tau_3v(orders, Q, S, isolated=1, beta_pre=0, beta_post=0, beta_coarse=0)
+    assert np.abs(Qout - Q).max() == 0.0
+    scale = np.abs(S).max()
+    assert np.nanmax(tau[:, 1:, :]) < 1e-10 * scale
+    assert np.nanmax(tau[:, 0, 1:]) < 1e-10 * scale       # N1 = 2, 3, 4
+    assert np.nanmin(tau[:, 0, 0]) > 1e-4 * scale         # N1 = 1: the quadratic energy is not representable
+    assert np.isnan(tau[:, 1:, 3]).all()                  # N2, N3 = 4 = P: not estimated
+
+
+@pytest.mark.parametrize("family", [LG, LGL])
+def test_isolated_equals_dg_for_continuous_state(oracle_mod, family):
+    """A state whose W = (u, v, w, T) is linear and whose conserved variables are polynomials of degree <= N
+    is continuous with continuous gradients, so every numerical flux reduces to the physical one and the DG
+    operator equals the isolated operator on elements whose neighbours do not touch the boundary."""
+    mach = 0.3
+    mesh = I.box_mesh((5, 5, 5), (0, 0, 0), (1, 1, 1), M=(1, 1, 1), periodic=(False,) * 3)
+    orders = I.uniform_orders(mesh.K, (3, 2, 3))
+    o = oracle_mod.Oracle(mesh, I.Physics(mach=mach, reynolds=50.0, family=family))
+    X = o.geometry(orders)[0]
+    x, y, z = X
+    Q = I.conserved(np.ones_like(x), 0.5 + 0.2 * y, 0.1 * z - 0.05 * x, 0.1 * x,
+                    1 / (1.4 * mach ** 2) * (1 + 0.02 * x - 0.01 * y))
+    A = o.operator(orders, Q)
+    Ah = o.operator(orders, Q, isolated=True)
+    off = I.node_offsets(orders)
+    e = 2 + 5 * (2 + 5 * 2)  # the centre element
+    s = slice(off[e], off[e + 1])
+    # round-off scale of the cancelling flux terms: p_inf (N+1)^2 / h
+    scale = 1 / (1.4 * mach ** 2) * 16 / 0.2
+    assert np.abs(A[:, s] - Ah[:, s]).max() < 1e-12 * scale
+    assert np.abs(A - Ah).max() > 1e-6 * np.abs(Ah).max()  # boundary elements do differ
+
+
+# ------------------------------------------------------------------------------------------------------
+# Sec. 3.1-3.2.3: FAS fixed point and the level-by-level estimator
+# ------------------------------------------------------------------------------------------------------
+def test_fas_fixed_point_and_one_shot_tau(oracle_mod):
+    base = I.box_mesh((2, 2, 2), (-1, -1, -1), (1, 1, 1), M=(2, 2, 2), wobble=0.1)
+    mesh, orders = I.reorient(base, 2, period=(2, 2, 2), orders=I.random_orders(base.K, 2, 5, 8))
+    ph = I.Physics(mach=0.3, reynolds=80.0)
+    o = oracle_mod.Oracle(mesh, ph)
+    nn = int(I.node_offsets(orders)[-1])
+    Q = I.perturbed_freestream(nn, 0.3, 0.02, 6)
+    S = o.operator(orders, Q)  # makes Q the exact discrete steady solution: r = 0
+    Q1, r = o.vcycles(orders, Q, S, ncycles=1, beta_pre=2, beta_post=2, beta_coarse=3)
+    assert np.abs(Q1 - Q).max() < 1e-11 * np.abs(Q).max()
+    for iso in (0, 1):
+        tau, _ = o.tau_3v(orders, Q, S, isolated=iso, beta_pre=1, beta_post=1, beta_coarse=1)
+        for d in range(3):
+            for n in range(1, int(orders[:, d].max())):
+                oc = orders.copy()
+                oc[:, d] = np.minimum(oc[:, d], n)
+                Qc = o.transfer(orders, oc, Q, prolong=False)
+                Sc = o.transfer(orders, oc, S, prolong=False)
+                t1 = Sc - o.operator(oc, Qc, isolated=bool(iso))
+                off = I.node_offsets(oc)
+                for e in range(mesh.K):
+                    if orders[e, d] <= n:
+                        assert np.isnan(tau[e, d, n - 1])
+                        continue
+                    ref = np.abs(t1[:, off[e]:off[e + 1]]).max()
+                    assert abs(tau[e, d, n - 1] - ref) <= 1e-9 * max(ref, 1e-3 * np.abs(S).max()), (iso, d, n, e)
+
+
+def test_zero_sweeps_leave_state_unchanged(oracle_mod):
+    wl = I.config_box()
+    o = oracle_mod.Oracle(wl.mesh, wl.phys)
+    Q1, _ = o.vcycles(wl.orders, wl.Q, caps=[3, 2, 1], beta_pre=0, beta_post=0, beta_coarse=0)
+    assert np.array_equal(Q1, wl.Q)
+
+
+def test_vcycles_reduce_residual_near_steady_state(oracle_mod):
+    wl = I.config_box()
+    o = oracle_mod.Oracle(wl.mesh, wl.phys)
+    Q = I.perturbed_freestream(wl.n_nodes, 0.1, 1e-3, 5)
+    r0 = np.abs(o.residual(wl.orders, Q)).max()
+    Q, r = o.vcycles(wl.orders, Q, caps=[3, 2, 1], ncycles=3, beta_pre=5, beta_post=5, beta_coarse=10)
+    assert r < 0.05 * r0
+
+
+# ------------------------------------------------------------------------------------------------------
+# Invariance: element numbering and element reference frames do not change the physical residual
+# ------------------------------------------------------------------------------------------------------
+def test_invariance_renumbering_and_frames(oracle_mod):
+    base = I.box_mesh((3, 2, 2), (-1, -1, -1), (1, 1, 1), M=(2, 2, 2), wobble=0.12)
+    ph = I.Physics(mach=0.3, reynolds=60.0)
+    N = 4
+    o1 = oracle_mod.Oracle(base, ph)
+    orders = I.uniform_orders(base.K, (N, N, N))
+    X1 = o1.geometry(orders)[0]
+    field = lambda X: I.conserved(1 + 0.05 * np.sin(np.pi * X[0]), 0.8 + 0.05 * np.cos(np.pi * X[1]),
+                                  0.05 * np.sin(np.pi * X[2]), 0.0 * X[0], 1 / (1.4 * 0.09) * (1 + 0.02 * X[1]))
+    R1 = o1.residual(orders, field(X1))
+    mesh2, _ = I.reorient(base, 5, period=(2, 2, 2))
+    o2 = oracle_mod.Oracle(mesh2, ph)
+    X2 = o2.geometry(orders)[0]
+    R2 = o2.residual(orders, field(X2))
+    key = lambda X: np.lexsort(np.round(X, 9)[::-1])
+    i1, i2 = key(X1), key(X2)
+    assert np.abs(X1[:, i1] - X2[:, i2]).max() < 1e-12
+    assert np.abs(R1[:, i1] - R2[:, i2]).max() < 1e-10 * np.abs(R1).max()
+    # renumbering elements
+    perm = np.random.default_rng(0).permutation(base.K)
+    inv = np.argsort(perm)
+    nbr = base.nbr_elem[perm]
+    nbr = np.where(nbr >= 0, inv[np.maximum(nbr, 0)], -1)
+    mesh3 = I.Mesh(base.K, base.M, base.gnodes[perm], nbr, base.nbr_face[perm], base.orient[perm], base.bc[perm])
+    o3 = oracle_mod.Oracle(mesh3, ph)
+    X3 = o3.geometry(orders)[0]
+    R3 = o3.residual(orders, field(X3))
+    i3 = key(X3)
+    assert np.abs(R1[:, i1] - R3[:, i3]).max() < 1e-10 * np.abs(R1).max()
+
+
+def test_plate_z_uniform(oracle_mod):
+    wl = I.config_plate(8, 4, amp=0.0)
+    o = oracle_mod.Oracle(wl.mesh, wl.phys)
+    X = o.geometry(wl.orders)[0]
+    Q = I.conserved(1 + 0.01 * np.sin(3 * X[0]), 1 - 0.1 * np.exp(-X[1] * 20), 0.01 * X[1], 0 * X[0],
+                    1 / (1.4 * 0.04) * np.ones_like(X[0]))
+    R = o.residual(wl.orders, Q)
+    assert np.abs(R[3]).max() < 1e-9 * np.abs(R).max()
+    off = I.node_offsets(wl.orders)
+    for e in range(wl.mesh.K):
+        r = R[:, off[e]:off[e + 1]].reshape(5, 2, 7, 7)
+        assert np.abs(r[:, 0] - r[:, 1]).max() < 1e-9 * np.abs(R).max()
