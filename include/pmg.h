@@ -1,0 +1,187 @@
+/*
+ * pmg: MI355X-native DGSEM compressible Navier-Stokes residual, FAS p-multigrid and in-cycle anisotropic
+ * truncation-error estimation, behind a plain C ABI.
+ *
+ * Method: Rueda-Ramirez, Manzanero, Ferrer, Rubio, Valero, "A p-Multigrid Strategy with Anisotropic
+ * p-Adaptation Based on Truncation Errors for High-Order Discontinuous Galerkin Methods" (J. Comput.
+ * Phys.), cited below by section and equation.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Problem (Sec. 3.1, eq. NonLinFAS): find the nodal solution Q of A(Q) = S, where A = [M]^{-1} F is the
+ *   DGSEM spatial operator (Sec. 2, eqs. DiscretNSElem/DiscretNS) of the non-dimensional compressible
+ *   Navier-Stokes equations (Appendix A) and S the nodal source.  The residual is r = S - A(Q)
+ *   (eq. nonlinRes).
+ * - Elements are hexahedra with reference coordinates (xi, eta, zeta) in [-1,1]^3 and per-element,
+ *   per-direction orders (N1, N2, N3), 1 <= N_d <= 7.  Element e holds (N1+1)(N2+1)(N3+1) nodes numbered
+ *   i + (N1+1)(j + (N2+1) k), xi fastest.  Node family: Legendre-Gauss (the paper's) or Gauss-Lobatto.
+ * - State arrays are FP64, variable-major "[5][n_nodes]": all rho values, then rho u, rho v, rho w,
+ *   rho e; nodes of element 0 first, then element 1, ...  pmg_state_layout gives n_nodes and offsets.
+ * - Faces are numbered 0..5 = xi-, xi+, eta-, eta+, zeta-, zeta+.  Face-local coordinates (s, t) are the two
+ *   tangential reference coordinates in increasing axis order.  Orientation code o (0..7) of face f of
+ *   element e towards its neighbour face f' maps (s, t) on e's face to (s', t') on the neighbour's face:
+ *   (u, v) = (t, s) if (o & 4) else (s, t); s' = -u if (o & 1) else u; t' = -v if (o & 2) else v.
+ * - Boundary tags: 0 interior or periodic (has a neighbour), 1 no-slip adiabatic wall, 2 far field,
+ *   3 free-slip wall.  Far field is rho = 1, v = (1, 0, 0), p = 1 / (gamma M^2).
+ * - Pointers named *_dev are device pointers on the solver's GPU; the caller owns them (for example the
+ *   data_ptr() of torch tensors) and keeps them alive until the stream has consumed them.  Host arrays
+ *   are copied during the call and may be freed afterwards.  The library owns its handles and every
+ *   internal device buffer (metrics, level states, face arrays).
+ * - stream is a hipStream_t (NULL = the default stream).  Every call is asynchronous on it, except that a
+ *   non-NULL host out-pointer (res_inf_host, dt_host, ...) makes the call wait for its result.
+ * - Every call returns a pmg_status; on failure pmg_last_error() describes it (thread-local text, valid
+ *   until the next call on the same thread).  No C++ exception crosses the ABI.  Handles are not
+ *   thread-safe: use one handle per thread, or serialise.
+ */
+#ifndef PMG_H
+#define PMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PMG_OK = 0,
+  PMG_ERR_INVALID_ARG = 1,   /* a size, order, table entry or pointer is out of range */
+  PMG_ERR_OOM = 2,           /* device allocation failed */
+  PMG_ERR_HIP = 3,           /* a HIP runtime call failed */
+  PMG_ERR_NONPHYSICAL = 4,   /* non-finite residual, or rho <= 0 / p <= 0 detected at a sync point */
+  PMG_ERR_NOT_CONVERGED = 5, /* pmg_solve reached max_cycles */
+  PMG_ERR_BUSY = 6,
+  PMG_ERR_UNIMPLEMENTED = 7
+} pmg_status;
+
+typedef struct pmg_ctx_s* pmg_ctx;       /* one GPU */
+typedef struct pmg_mesh_s* pmg_mesh;     /* geometry + connectivity, copied to the GPU */
+typedef struct pmg_solver_s* pmg_solver; /* mesh + order tensor + physics + multigrid hierarchy */
+
+/* Physics (Appendix A; CFL constants of Sec. 2). */
+typedef struct {
+  double mach;        /* far-field Mach number M */
+  double reynolds;    /* far-field Reynolds number Re */
+  double prandtl;     /* 0.72 */
+  double gamma;       /* 1.4 */
+  double sutherland;  /* Sutherland constant over the reference temperature, 110.4 / 288.15 */
+  double cfl_adv;     /* C^a of the advective step limit */
+  double cfl_visc;    /* C^nu of the diffusive step limit */
+  int32_t node_family;     /* 0 Legendre-Gauss, 1 Legendre-Gauss-Lobatto */
+  int32_t viscosity_model; /* 0 Sutherland's law, 1 constant viscosity */
+} pmg_physics;
+
+/* FAS p-multigrid (Sec. 3.1, Algorithm "FAS: V-Cycle"; Secs. 3.1.1-3.1.2; Sec. 3.2.4). */
+typedef struct {
+  int32_t n_levels;          /* number of isotropic levels; 0 = max order (Delta N = 1 down to order 1) */
+  const int32_t* level_caps; /* host, n_levels entries finest first, e.g. {3, 1}; NULL = max, max-1, ..., 1.
+                                Level with cap c holds min(N_d, c) in every direction (high-order coarsening). */
+  int32_t beta_pre;          /* pre-smoothing RK3 sweeps (beta_1, or beta_1^0 with tuning) */
+  int32_t beta_post;         /* post-smoothing sweeps (beta_2, or beta_2^0 with tuning) */
+  int32_t beta_coarse;       /* sweeps on the coarsest level (replace pre + post there) */
+  int32_t tuning;            /* 0 fixed sweeps; 1 residual-based tuning of Sec. 3.1.2 */
+  double eta;                /* pre-smoothing tuning factor (1.1) */
+  int32_t max_repeats;       /* cap on tuning repetitions per smoothing phase */
+  int32_t fmg;               /* 1: pmg_solve starts with a full-multigrid ramp */
+  double fmg_threshold;      /* residual that raises the FMG level (1e-1 plate, 1.0 sphere) */
+} pmg_mg_params;
+
+const char* pmg_last_error(void);
+
+pmg_status pmg_ctx_create(int hip_device, pmg_ctx* out);
+void pmg_ctx_destroy(pmg_ctx ctx);
+
+/*
+ * Mesh (Sec. 2, eq. mapping): K hexahedra with a tensor-product Lagrange mapping of degree M = (M1,M2,M3)
+ * (1 <= M_d <= 4), given by its values at equispaced reference nodes.
+ *   geom_nodes: host, K*(M1+1)*(M2+1)*(M3+1)*3 doubles, [e][k][j][i][xyz] (xi index i fastest).
+ *   nbr_elem:   host, K*6, neighbour element of each face, -1 on a boundary face.
+ *   nbr_face:   host, K*6, the neighbour's face number.
+ *   orient:     host, K*6, orientation code towards the neighbour (see above).
+ *   bc:         host, K*6, boundary tag (0 where a neighbour exists).
+ * Errors: PMG_ERR_INVALID_ARG for inconsistent connectivity (neighbour not pointing back, codes out of
+ * range, boundary face tagged 0).
+ */
+pmg_status pmg_mesh_create(pmg_ctx ctx, int64_t K, const int32_t M[3], const double* geom_nodes,
+                           const int64_t* nbr_elem, const int32_t* nbr_face, const int32_t* orient,
+                           const int32_t* bc, pmg_mesh* out);
+void pmg_mesh_destroy(pmg_mesh mesh);
+
+/*
+ * Solver: mesh + order tensor (host, K*3 int32, each 1..7) + physics + multigrid parameters.  Builds the
+ * isotropic level hierarchy (high-order coarsening, Sec. 3.2.4) and, lazily, the three one-direction
+ * hierarchies of the anisotropic cycle (Sec. 3.2.3).  Metric terms are computed on the GPU for every
+ * level's own orders (curl form, Sec. 2).  The mesh must outlive the solver.
+ */
+pmg_status pmg_solver_create(pmg_ctx ctx, pmg_mesh mesh, const int32_t* orders, const pmg_physics* phys,
+                             const pmg_mg_params* mg, pmg_solver* out);
+void pmg_solver_destroy(pmg_solver s);
+
+/* n_nodes = sum_e (N1+1)(N2+1)(N3+1) (the paper's DOF count); elem_node_offset (host, K+1, nullable). */
+pmg_status pmg_state_layout(pmg_solver s, int64_t* n_nodes, int64_t* elem_node_offset);
+
+/* Q_dev[5][n_nodes] <- the far-field state. */
+pmg_status pmg_init_freestream(pmg_solver s, double* Q_dev, void* stream);
+
+/*
+ * Residual r = S - A(Q) on the finest level (eq. nonlinRes).  op = 0: DGSEM operator with Roe advective
+ * and Bassi-Rebay 1 viscous numerical fluxes, mortars on p-nonconforming faces (Sec. 2, eq. weak2);
+ * op = 1: isolated operator, every numerical flux replaced by the element's own physical flux
+ * (Sec. 3.2.1, eq. IsolTruncErrorSteady).  S_dev may be NULL (S = 0).  R_dev[5][n_nodes] is written.
+ * res_inf_host (nullable) receives max |r| over nodes and variables (waits for the stream).
+ */
+pmg_status pmg_residual(pmg_solver s, int op, const double* Q_dev, const double* S_dev, double* R_dev,
+                        double* res_inf_host, void* stream);
+
+/* CFL step of Sec. 2 for Q on the finest level: min over nodes and directions of
+ * min(C^a h_d / ((|v| + c) N_d^2), C^nu h_d^2 / (nu N_d^4)), h_d = 2 J / |J a^d|, nu = mu / (rho Re). */
+pmg_status pmg_timestep(pmg_solver s, const double* Q_dev, double* dt_host, void* stream);
+
+/* 'sweeps' sweeps of Williamson's low-storage RK3 (Sec. 3.1) on the finest level, the step recomputed
+ * from Q at the start of each sweep: G <- a_s G + dt r(Q); Q <- Q + b_s G. */
+pmg_status pmg_smooth(pmg_solver s, double* Q_dev, const double* S_dev, int sweeps, void* stream);
+
+/*
+ * Level hierarchy.  hierarchy = -1 for the isotropic one, 0/1/2 for the one that coarsens only xi/eta/zeta.
+ * Level index 0 is the coarsest; the last is the finest (the solver's orders).  pmg_level_info returns the
+ * number of levels when level < 0, else that level's node count and (nullable) its orders (host K*3).
+ */
+pmg_status pmg_level_info(pmg_solver s, int hierarchy, int level, int32_t* n_levels, int64_t* n_nodes,
+                          int32_t* orders);
+/* L2 projection (restriction, eqs. FASCoarseSol/FASCoarseRes) of U from level 'level' to level-1, and
+ * exact interpolation (prolongation, eq. FASCorrectSol) from 'level' to level+1; [5][n] arrays. */
+pmg_status pmg_restrict(pmg_solver s, int hierarchy, int level, const double* Ufine_dev, double* Ucoarse_dev,
+                        void* stream);
+pmg_status pmg_prolong(pmg_solver s, int hierarchy, int level, const double* Ucoarse_dev, double* Ufine_dev,
+                       void* stream);
+
+/*
+ * n_cycles isotropic FAS V-cycles (Algorithm "FAS: V-Cycle" with iteration error eps = Q~ - Q~_0,
+ * eq. FASIterError) on Q_dev (in/out) with physical source S_dev (nullable).  res_inf_host (nullable)
+ * receives max |S - A(Q)| after the last cycle.
+ */
+pmg_status pmg_vcycle(pmg_solver s, double* Q_dev, const double* S_dev, int n_cycles, double* res_inf_host,
+                      void* stream);
+
+/* Steady solve: optional FMG start, then V-cycles until max |r| < tol (checked on the host after every
+ * cycle).  Returns PMG_ERR_NOT_CONVERGED when max_cycles is reached first. */
+pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double tol, int max_cycles, int* cycles_out,
+                     double* res_inf_out, void* stream);
+
+/*
+ * Anisotropic truncation-error estimate inside the multigrid cycle (Secs. 3.2.1-3.2.3, eqs. TruncError!
+ * and AnisTruncError): one V-cycle per direction d, coarsening only d ("3V" cycle), each starting from the
+ * previous one's result; Q_dev is smoothed in place by the three cycles.  At the entry of each coarse level
+ * with cap n, tau = S_phys - A^n(I Q~) (isolated = 0, reusing the coarse-source operator evaluation) or
+ * tau^ = S_phys - A^^n(I Q~) (isolated = 1), S_phys the physical source restricted level by level.
+ * tau_map_dev: device, K*3*nt doubles with nt = (max order) - 1, [e][d][n-1] = max over the element's nodes
+ * and variables of |tau| for n < N_d^e, NaN otherwise.  Sweeps per level come from the solver's params.
+ */
+pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, int isolated, double* tau_map_dev,
+                            void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMG_H */

@@ -186,3 +186,11 @@ void ora_gradient(or_problem* P, const int32_t* ord, int isolated, const double*
   or_gradient(P, L, isolated, Q, gW);
   or_level_destroy(L);
 }
+
+/* Operator and the per-entry magnitude of its terms (round-off scale). */
+void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const double* Q, double* A, double* scale);
+void ora_operator_scale(or_problem* P, const int32_t* ord, int isolated, const double* Q, double* A, double* scale) {
+  or_level* L = or_level_create(P, ord);
+  or_operator_ex(P, L, isolated, Q, A, scale);
+  or_level_destroy(L);
+}

@@ -96,13 +96,18 @@ or_level* or_level_create(const or_problem* P, const int32_t* ord) {
       for (int d = 0; d < 3; d++) deriv(b, n, d, X + m * npe, dX + (m * 3 + d) * npe);
 
     double* Ja = (double*)calloc(9 * npe, sizeof(double)); /* Ja[(i*3 + comp)*npe + node] */
+    /* The curl form is unchanged when X is shifted by a constant (the discrete curl of a discrete gradient
+     * vanishes), so it is evaluated on coordinates relative to the element's first mapping node: the
+     * products then carry round-off relative to the element size, not to the distance from the origin. */
+    const double x0[3] = {g[0], g[1], g[2]};
     /* invariant curl form, component n_ of every J a^i */
     for (int nc = 0; nc < 3; nc++) {
       int mc = (nc + 1) % 3, lc = (nc + 2) % 3;
       /* V_c = X_l dX_m/dxi_c - X_m dX_l/dxi_c at the nodes (I^N of the product) */
       for (int c = 0; c < 3; c++)
         for (int p = 0; p < npe; p++)
-          V[c * npe + p] = X[lc * npe + p] * dX[(mc * 3 + c) * npe + p] - X[mc * npe + p] * dX[(lc * 3 + c) * npe + p];
+          V[c * npe + p] = (X[lc * npe + p] - x0[lc]) * dX[(mc * 3 + c) * npe + p] -
+                           (X[mc * npe + p] - x0[mc]) * dX[(lc * 3 + c) * npe + p];
       /* (curl V)_1 = d2 V3 - d3 V2; (curl V)_2 = d3 V1 - d1 V3; (curl V)_3 = d1 V2 - d2 V1 */
       for (int i = 0; i < 3; i++) {
         int a = (i + 1) % 3, bb = (i + 2) % 3;

@@ -76,6 +76,7 @@ def lib():
         L.ora_rk3_linear.restype = C.c_double
         L.ora_rk3_linear.argtypes = [C.c_double, C.c_double, C.c_double]
         L.ora_gradient.argtypes = [P, I32, C.c_int, D, D]
+        L.ora_operator_scale.argtypes = [P, I32, C.c_int, D, D, D]
         L.ora_solve.restype = C.c_int
         L.ora_solve.argtypes = [P, I32, C.c_int, I32, C.POINTER(MGParams), D, D, C.c_double, C.c_int, D, D]
         _lib = L
@@ -195,6 +196,14 @@ class Oracle:
         A = np.zeros_like(Q)
         lib().ora_operator(self.h, _i32(self._ord(orders)), int(isolated), _d(Q), _d(A))
         return A
+
+    def operator_scale(self, orders, Q, isolated=False):
+        """(A, scale): scale[v, node] = sum of |terms| entering A[v, node] (its round-off scale)."""
+        Q = _f64(Q)
+        A = np.zeros_like(Q)
+        sc = np.zeros_like(Q)
+        lib().ora_operator_scale(self.h, _i32(self._ord(orders)), int(isolated), _d(Q), _d(A), _d(sc))
+        return A, sc
 
     def residual(self, orders, Q, S=None, isolated=False):
         Q = _f64(Q)

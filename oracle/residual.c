@@ -336,7 +336,9 @@ void or_gradient(const or_problem* P, const or_level* L, int isolated, const dou
   free(Ws);
 }
 
-void or_operator(const or_problem* P, const or_level* L, int isolated, const double* Q, double* A) {
+/* A(Q); when 'scale' is given it receives, per node and variable, the sum of the magnitudes of the terms
+ * that make up A (the round-off scale of that entry, divided by J like A itself). */
+void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const double* Q, double* A, double* scale) {
   const or_phys* ph = &P->ph;
   const int64_t nn = L->nn, nf = L->nf;
   double* qf = malloc(sizeof(double) * 5 * nf);
@@ -465,7 +467,7 @@ void or_operator(const or_problem* P, const or_level* L, int isolated, const dou
         for (int i = 0; i < n[0]; i++) {
           int ijk[3] = {i, j, k3};
           int64_t p = vidx(n, i, j, k3);
-          double s[5] = {0, 0, 0, 0, 0};
+          double s[5] = {0, 0, 0, 0, 0}, sa[5] = {0, 0, 0, 0, 0};
           for (int d = 0; d < 3; d++) {
             const or_basis1d* bd = b[d];
             int id = ijk[d];
@@ -474,21 +476,33 @@ void or_operator(const or_problem* P, const or_level* L, int isolated, const dou
               q3[d] = m;
               int64_t pm = vidx(n, q3[0], q3[1], q3[2]);
               double Dh = -bd->D[m][id] * bd->w[m] / bd->w[id];
-              for (int v = 0; v < 5; v++) s[v] += Dh * Ft[(d * 5 + v) * npe + pm];
+              for (int v = 0; v < 5; v++) {
+                s[v] += Dh * Ft[(d * 5 + v) * npe + pm];
+                sa[v] += fabs(Dh * Ft[(d * 5 + v) * npe + pm]);
+              }
             }
             int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
             int64_t fk = ijk[t1] + (int64_t)n[t1] * ijk[t2];
             for (int side = 0; side < 2; side++) {
               int64_t fi = L->fo[6 * e + 2 * d + side] + fk;
               double l = side ? bd->lp[id] : bd->lm[id];
-              for (int v = 0; v < 5; v++) s[v] += l * Phi[v * nf + fi] / bd->w[id];
+              for (int v = 0; v < 5; v++) {
+                s[v] += l * Phi[v * nf + fi] / bd->w[id];
+                sa[v] += fabs(l * Phi[v * nf + fi] / bd->w[id]);
+              }
             }
           }
           for (int v = 0; v < 5; v++) A[v * nn + o + p] = s[v] / L->J[o + p];
+          if (scale)
+            for (int v = 0; v < 5; v++) scale[v * nn + o + p] = sa[v] / fabs(L->J[o + p]);
         }
     free(Ft);
   }
   free(qf); free(gW); free(gf); free(Phi);
+}
+
+void or_operator(const or_problem* P, const or_level* L, int isolated, const double* Q, double* A) {
+  or_operator_ex(P, L, isolated, Q, A, NULL);
 }
 
 /*

@@ -1,0 +1,198 @@
+// Device-side building blocks: basis tables in constant memory, level descriptors, and the pointwise
+// physics of the compressible Navier-Stokes equations (paper, Appendix A) with the Roe flux (Sec. 2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PMG_MAXN 8        // nodes per direction (order <= 7)
+#define PMG_BLOCK 256     // threads per element / face tile
+#define PMG_TILE_MAX 512  // nodes per element tile (one element of 8x8x8)
+#define PMG_NPT 2         // nodes per thread = PMG_TILE_MAX / PMG_BLOCK
+#define PMG_FACE_TILE 256 // mortar nodes per face tile
+#define PMG_MAX_TILE_ELEMS 64
+
+// 1-D tables of one node family, indexed by the number of nodes n = order + 1 (1..8).
+struct BasisTables {
+  double x[PMG_MAXN + 1][PMG_MAXN];
+  double w[PMG_MAXN + 1][PMG_MAXN];
+  double D[PMG_MAXN + 1][PMG_MAXN][PMG_MAXN];     // D[n][i][j] = l_j'(x_i)
+  double Dhat[PMG_MAXN + 1][PMG_MAXN][PMG_MAXN];  // Dhat[n][i][m] = -D[m][i] w_m / w_i (weak form)
+  double lm[PMG_MAXN + 1][PMG_MAXN], lp[PMG_MAXN + 1][PMG_MAXN];  // l_i(-1), l_i(+1)
+  double Lm[PMG_MAXN + 1][PMG_MAXN], Lp[PMG_MAXN + 1][PMG_MAXN];  // surface lift l_i(-+1) / w_i
+};
+
+__constant__ BasisTables c_tab[2];  // [family]
+
+// Transfer matrices T(from, to) of one family, row-major [to][from]: exact interpolation when to > from,
+// L2 projection with the 'from' quadrature when to < from, identity when equal.  Global memory.
+__device__ __forceinline__ const double* tmat(const double* T, int from, int to) {
+  return T + ((from * (PMG_MAXN + 1) + to) * PMG_MAXN * PMG_MAXN);
+}
+#define TMAT_STRIDE ((PMG_MAXN + 1) * (PMG_MAXN + 1) * PMG_MAXN * PMG_MAXN)
+
+struct Phys {
+  double gamma, gm1, gM2, Re, invRe, kcoef, suth, suth1, cfl_adv, cfl_visc;
+  double pinf, rhoE_inf;
+  int visc_const, family;
+};
+
+// Interface between two element faces (master = lower element id; the lower face on self-periodic faces).
+struct FaceRec {
+  int eM, fM, eS, fS;  // eS = -1 on boundary faces
+  int o, bc;
+  int foM, foS;        // first face node of each side in the face arrays
+  int nMs, nMt;        // master face nodes along its (s, t) axes
+  int nS1, nS2;        // slave face nodes along its own axes
+  int ms, mt;          // mortar nodes along the master (s, t) axes
+  int mbase;           // first mortar node
+  int flags;           // bit0 master side equals the mortar, bit1 slave side equals the mortar
+};
+
+struct LevelDev {
+  int K, nn, nf, nm, fam;
+  const int* __restrict__ ord;   // K*3 orders
+  const int* __restrict__ off;   // K+1 node offsets
+  const int* __restrict__ fo;    // K*6 face-node offsets
+  const double* __restrict__ Ja;   // [9][nn]  (J a^d)_c at [(d*3 + c)]
+  const double* __restrict__ invJ; // [nn]
+  const double* __restrict__ J;    // [nn]
+  const double* __restrict__ Nout; // [3][nf] outward normal x surface Jacobian, own side
+  const int4* __restrict__ tiles;  // {first, count, packed n1|n2<<8|n3<<16, nodes}
+  const int* __restrict__ elist;
+  const FaceRec* __restrict__ faces;
+  const int* __restrict__ mface;   // mortar node -> face
+  const int* __restrict__ ftile;   // face tile boundaries in mortar nodes
+  const double* __restrict__ mgeo; // [4][nm] unit normal (master outward) and surface Jacobian
+  const double* __restrict__ T;    // transfer tables of this family
+};
+
+// ------------------------------------------------------------------------------------------------
+// Pointwise physics
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void prim(const Phys& P, const double q[5], double& rho, double v[3], double& p,
+                                     double& T) {
+  rho = q[0];
+  double ir = 1.0 / q[0];
+  v[0] = q[1] * ir;
+  v[1] = q[2] * ir;
+  v[2] = q[3] * ir;
+  p = P.gm1 * (q[4] - 0.5 * (q[1] * v[0] + q[2] * v[1] + q[3] * v[2]));
+  T = P.gM2 * p * ir;
+}
+
+__device__ __forceinline__ double mu_of(const Phys& P, double T) {
+  if (P.visc_const) return 1.0;
+  return T * sqrt(T) * P.suth1 / (T + P.suth);
+}
+
+__device__ __forceinline__ void prim_w(const Phys& P, const double q[5], double W[4]) {
+  double rho, v[3], p, T;
+  prim(P, q, rho, v, p, T);
+  W[0] = v[0]; W[1] = v[1]; W[2] = v[2]; W[3] = T;
+}
+
+// F^a . N for an arbitrary vector N (5 components)
+__device__ __forceinline__ void flux_adv_n(const Phys& P, const double q[5], const double N[3], double out[5]) {
+  double rho, v[3], p, T;
+  prim(P, q, rho, v, p, T);
+  double vn = v[0] * N[0] + v[1] * N[1] + v[2] * N[2];
+  out[0] = q[0] * vn;
+  out[1] = q[1] * vn + p * N[0];
+  out[2] = q[2] * vn + p * N[1];
+  out[3] = q[3] * vn + p * N[2];
+  out[4] = vn * (q[4] + p);
+}
+
+// Viscous flux tensor F^v[c][v] (row v = 0 is zero and not stored: F[c][0..3] = momentum, energy)
+// g[k*3 + c] = dW_k / dx_c, W = (u, v, w, T).  wall: no-slip adiabatic wall flux (no work, no heat flux).
+__device__ __forceinline__ void flux_visc(const Phys& P, const double q[5], const double g[12], bool wall,
+                                          double F[3][4]) {
+  double rho, v[3], p, T;
+  prim(P, q, rho, v, p, T);
+  double mu = mu_of(P, T);
+  double div = g[0] + g[4] + g[8];
+  double lam = -2.0 / 3.0 * mu * div;
+  double tau[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; i++)
+#pragma unroll
+    for (int j = 0; j < 3; j++) tau[i][j] = mu * (g[i * 3 + j] + g[j * 3 + i]);
+  tau[0][0] += lam; tau[1][1] += lam; tau[2][2] += lam;
+  double kap = mu * P.kcoef;
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    F[c][0] = P.invRe * tau[c][0];
+    F[c][1] = P.invRe * tau[c][1];
+    F[c][2] = P.invRe * tau[c][2];
+    F[c][3] = wall ? 0.0 : P.invRe * (v[0] * tau[c][0] + v[1] * tau[c][1] + v[2] * tau[c][2] + kap * g[9 + c]);
+  }
+}
+
+// Roe flux along the unit normal n (from L to R), standard Roe averages, no entropy fix.
+__device__ __forceinline__ void roe_flux(const Phys& P, const double qL[5], const double qR[5], const double n[3],
+                                         double Fn[5]) {
+  double rL, vL[3], pL, TL, rR, vR[3], pR, TR;
+  prim(P, qL, rL, vL, pL, TL);
+  prim(P, qR, rR, vR, pR, TR);
+  double HL = (qL[4] + pL) / rL, HR = (qR[4] + pR) / rR;
+  double sL = sqrt(rL), sR = sqrt(rR);
+  double isum = 1.0 / (sL + sR);
+  double rh = sL * sR;
+  double vh[3] = {(sL * vL[0] + sR * vR[0]) * isum, (sL * vL[1] + sR * vR[1]) * isum, (sL * vL[2] + sR * vR[2]) * isum};
+  double Hh = (sL * HL + sR * HR) * isum;
+  double v2 = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
+  double c2 = P.gm1 * (Hh - 0.5 * v2);
+  double ch = sqrt(c2);
+  double un = vh[0] * n[0] + vh[1] * n[1] + vh[2] * n[2];
+  double dr = rR - rL, dp = pR - pL;
+  double dv[3] = {vR[0] - vL[0], vR[1] - vL[1], vR[2] - vL[2]};
+  double dun = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
+  double i2c2 = 1.0 / (2.0 * c2);
+  double a1 = (dp - rh * ch * dun) * i2c2;
+  double a5 = (dp + rh * ch * dun) * i2c2;
+  double a2 = dr - dp / c2;
+  double l1 = fabs(un - ch), l5 = fabs(un + ch), l2 = fabs(un);
+  double d[5];
+  d[0] = l1 * a1 + l5 * a5 + l2 * a2;
+#pragma unroll
+  for (int c = 0; c < 3; c++)
+    d[1 + c] = l1 * a1 * (vh[c] - ch * n[c]) + l5 * a5 * (vh[c] + ch * n[c]) + l2 * a2 * vh[c] +
+               l2 * rh * (dv[c] - dun * n[c]);
+  d[4] = l1 * a1 * (Hh - un * ch) + l5 * a5 * (Hh + un * ch) + l2 * a2 * 0.5 * v2 +
+         l2 * rh * (vh[0] * dv[0] + vh[1] * dv[1] + vh[2] * dv[2] - un * dun);
+  double fl[5], fr[5];
+  flux_adv_n(P, qL, n, fl);
+  flux_adv_n(P, qR, n, fr);
+#pragma unroll
+  for (int k = 0; k < 5; k++) Fn[k] = 0.5 * (fl[k] + fr[k]) - 0.5 * d[k];
+}
+
+__device__ __forceinline__ void freestream(const Phys& P, double q[5]) {
+  q[0] = 1.0; q[1] = 1.0; q[2] = 0.0; q[3] = 0.0; q[4] = P.rhoE_inf;
+}
+
+// ghost state of a boundary node (unit outward normal n)
+__device__ __forceinline__ void ghost_state(const Phys& P, int bc, const double q[5], const double n[3], double g[5]) {
+  if (bc == 1) {
+    g[0] = q[0]; g[1] = -q[1]; g[2] = -q[2]; g[3] = -q[3]; g[4] = q[4];
+  } else if (bc == 3) {
+    double mn = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
+    g[0] = q[0]; g[1] = q[1] - 2.0 * mn * n[0]; g[2] = q[2] - 2.0 * mn * n[1]; g[3] = q[3] - 2.0 * mn * n[2];
+    g[4] = q[4];
+  } else {
+    freestream(P, g);
+  }
+}
+
+// non-negative doubles order like their bit patterns
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* a, double v) {
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void atomic_min_pos(unsigned long long* a, double v) {
+  atomicMin(a, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ void unpack3(int p, int& n1, int& n2, int& n3) {
+  n1 = p & 255; n2 = (p >> 8) & 255; n3 = p >> 16;
+}

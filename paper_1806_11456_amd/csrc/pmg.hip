@@ -1,0 +1,939 @@
+// pmg: MI355X (gfx950) implementation of the C-ABI declared in include/pmg.h.
+// One translation unit: device helpers and kernels are included below, then the host library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pmg.h"
+#include "device.h"
+#include "kernels_elem.inc"
+#include "kernels_face.inc"
+#include "kernels_setup.inc"
+#include "kernels_mg.inc"
+#include "host_basis.inc"
+
+// ------------------------------------------------------------------------------------------------
+// Errors
+// ------------------------------------------------------------------------------------------------
+namespace {
+thread_local std::string g_err;
+
+struct PmgError : std::runtime_error {
+  pmg_status st;
+  PmgError(pmg_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPCHECK(x)                                                                          \
+  do {                                                                                       \
+    hipError_t e_ = (x);                                                                     \
+    if (e_ != hipSuccess)                                                                    \
+      throw PmgError(e_ == hipErrorOutOfMemory ? PMG_ERR_OOM : PMG_ERR_HIP,                  \
+                     std::string(#x) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+#define REQUIRE(c, msg) \
+  do {                  \
+    if (!(c)) throw PmgError(PMG_ERR_INVALID_ARG, msg); \
+  } while (0)
+
+template <class F>
+pmg_status guard(F&& f) {
+  try {
+    f();
+    return PMG_OK;
+  } catch (const PmgError& e) {
+    g_err = e.what();
+    return e.st;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return PMG_ERR_INVALID_ARG;
+  } catch (...) {
+    g_err = "unknown error";
+    return PMG_ERR_INVALID_ARG;
+  }
+}
+
+inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
+
+// device allocation owned by a level / solver
+struct DevArena {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* alloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    HIPCHECK(hipMalloc(&p, n * sizeof(T)));
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = alloc<T>(v.size());
+    if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  ~DevArena() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+inline int pack3(int a, int b, int c) { return a | (b << 8) | (c << 16); }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// Handles
+// ------------------------------------------------------------------------------------------------
+struct pmg_ctx_s {
+  int device = 0;
+  DevArena arena;
+  double* T[2] = {nullptr, nullptr};  // transfer tables per family
+};
+
+struct pmg_mesh_s {
+  pmg_ctx ctx;
+  int64_t K;
+  int M[3];
+  std::vector<double> gnodes;
+  std::vector<int64_t> nbr;
+  std::vector<int32_t> nbrf, orient, bc;
+  DevArena arena;
+  double* d_gnodes = nullptr;
+};
+
+struct Level {
+  int K = 0, nn = 0, nf = 0, nm = 0, fam = 0;
+  std::vector<int> ord, off, fo;
+  int ntiles = 0, nftiles = 0, max_tile = 0;
+  DevArena arena;
+  int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile;
+  int4* d_tiles;
+  FaceRec* d_faces;
+  double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;
+  double *d_qf, *d_Ws, *d_gW, *d_gf, *d_PhiA, *d_Phi;
+  LevelDev dev;
+  size_t lds_grad() const { return (size_t)13 * max_tile * sizeof(double); }
+  size_t lds_div() const { return (size_t)15 * max_tile * sizeof(double); }
+};
+
+struct XferTiles {
+  DevArena arena;
+  int4* d_restrict = nullptr;  // from the finer level to the coarser one
+  int4* d_prolong = nullptr;   // from the coarser level to the finer one
+  int* d_elist = nullptr;
+  int ntiles = 0, lds_stride = 0;
+};
+
+struct Hier {
+  int dir = -1;
+  std::vector<std::shared_ptr<Level>> lv;  // 0 = coarsest
+  std::vector<int> caps;                   // per level index
+  std::vector<double*> Q, Q0, S, r, Sp, G, R;
+  std::vector<std::unique_ptr<XferTiles>> xf;  // xf[l]: pair (l, l+1)
+  DevArena arena;
+  int top() const { return (int)lv.size() - 1; }
+};
+
+struct pmg_solver_s {
+  pmg_ctx ctx;
+  pmg_mesh mesh;
+  Phys phys;
+  pmg_mg_params mg;
+  std::vector<int> orders;
+  std::shared_ptr<Level> top;
+  Hier iso;
+  std::unique_ptr<Hier> aniso[3];
+  DevArena arena;
+  unsigned long long* d_red = nullptr;  // reduction slots
+  double* d_zero = nullptr;             // [5][nn] zeros (absent source)
+  double* d_R = nullptr;                // [5][nn] top-level scratch residual
+  double* d_G = nullptr;                // [5][nn] top-level RK register
+  int nmax = 1;
+};
+
+// ------------------------------------------------------------------------------------------------
+// Level construction (Sec. 2 geometry; tiles and faces)
+// ------------------------------------------------------------------------------------------------
+static const int TILE_TARGET = 256;
+
+static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int>& ord) {
+  pmg_mesh m = s->mesh;
+  auto L = std::make_shared<Level>();
+  const int K = (int)m->K;
+  L->K = K;
+  L->fam = s->phys.family;
+  L->ord = ord;
+  L->off.assign(K + 1, 0);
+  L->fo.assign(6 * K, 0);
+  int64_t nn = 0, nf = 0;
+  for (int e = 0; e < K; e++) {
+    int n1 = ord[3 * e] + 1, n2 = ord[3 * e + 1] + 1, n3 = ord[3 * e + 2] + 1;
+    L->off[e] = (int)nn;
+    nn += (int64_t)n1 * n2 * n3;
+    const int fs[3] = {n2 * n3, n1 * n3, n1 * n2};
+    for (int f = 0; f < 6; f++) {
+      L->fo[6 * e + f] = (int)nf;
+      nf += fs[f / 2];
+    }
+  }
+  REQUIRE(5 * nn < (1ll << 31) && 12 * nf < (1ll << 31), "mesh too large for 32-bit node indexing");
+  L->off[K] = (int)nn;
+  L->nn = (int)nn;
+  L->nf = (int)nf;
+
+  // element tiles: elements bucketed by order triple
+  std::map<int, std::vector<int>> buckets;
+  for (int e = 0; e < K; e++) buckets[pack3(ord[3 * e] + 1, ord[3 * e + 1] + 1, ord[3 * e + 2] + 1)].push_back(e);
+  std::vector<int> elist;
+  std::vector<int4> tiles;
+  int max_tile = 1;
+  for (auto& kv : buckets) {
+    int n1 = kv.first & 255, n2 = (kv.first >> 8) & 255, n3 = kv.first >> 16;
+    int npe = n1 * n2 * n3;
+    int per = std::max(1, std::min(PMG_MAX_TILE_ELEMS, TILE_TARGET / npe));
+    const auto& es = kv.second;
+    for (size_t i = 0; i < es.size(); i += per) {
+      int cnt = (int)std::min<size_t>(per, es.size() - i);
+      tiles.push_back(make_int4((int)elist.size(), cnt, kv.first, cnt * npe));
+      max_tile = std::max(max_tile, cnt * npe);
+      for (int c = 0; c < cnt; c++) elist.push_back(es[i + c]);
+    }
+  }
+  REQUIRE(max_tile <= PMG_TILE_MAX, "element tile too large");
+  L->ntiles = (int)tiles.size();
+  L->max_tile = max_tile;
+
+  // faces: one record per interface (master side) and per boundary face
+  std::vector<FaceRec> faces;
+  for (int e = 0; e < K; e++)
+    for (int f = 0; f < 6; f++) {
+      int64_t g = m->nbr[6 * e + f];
+      int h = m->nbrf[6 * e + f];
+      bool master = g < 0 || e < g || (e == g && f < h);
+      if (!master) continue;
+      FaceRec F;
+      memset(&F, 0, sizeof(F));
+      int d = f / 2, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      F.eM = e; F.fM = f; F.o = g >= 0 ? m->orient[6 * e + f] : 0; F.bc = m->bc[6 * e + f];
+      F.foM = L->fo[6 * e + f];
+      F.nMs = ord[3 * e + t1] + 1;
+      F.nMt = ord[3 * e + t2] + 1;
+      if (g >= 0) {
+        F.eS = (int)g; F.fS = h;
+        int dg = h / 2, s1 = dg == 0 ? 1 : 0, s2 = dg == 2 ? 1 : 2;
+        F.foS = L->fo[6 * g + h];
+        F.nS1 = ord[3 * g + s1] + 1;
+        F.nS2 = ord[3 * g + s2] + 1;
+        int slave_s = (F.o & 4) ? F.nS2 : F.nS1, slave_t = (F.o & 4) ? F.nS1 : F.nS2;
+        F.ms = std::max(F.nMs, slave_s);
+        F.mt = std::max(F.nMt, slave_t);
+        int m1 = (F.o & 4) ? F.mt : F.ms, m2 = (F.o & 4) ? F.ms : F.mt;
+        F.flags = ((F.ms == F.nMs && F.mt == F.nMt) ? 1 : 0) | ((m1 == F.nS1 && m2 == F.nS2) ? 2 : 0);
+      } else {
+        F.eS = -1; F.fS = -1; F.foS = 0;
+        F.ms = F.nMs; F.mt = F.nMt;
+        F.flags = 1;
+      }
+      faces.push_back(F);
+    }
+  // order faces by mortar size (uniform lanes per tile), then pack into tiles of <= PMG_FACE_TILE lanes
+  std::stable_sort(faces.begin(), faces.end(),
+                   [](const FaceRec& a, const FaceRec& b) { return a.ms * a.mt > b.ms * b.mt; });
+  std::vector<int> ftile{0}, mface;
+  int cur = 0;
+  for (size_t i = 0; i < faces.size(); i++) {
+    int nmf = faces[i].ms * faces[i].mt;
+    if (cur + nmf > PMG_FACE_TILE) {
+      ftile.push_back((int)mface.size());
+      cur = 0;
+    }
+    faces[i].mbase = (int)mface.size();
+    for (int k = 0; k < nmf; k++) mface.push_back((int)i);
+    cur += nmf;
+  }
+  if (ftile.back() != (int)mface.size()) ftile.push_back((int)mface.size());
+  L->nftiles = (int)ftile.size() - 1;
+  L->nm = (int)mface.size();
+
+  std::vector<int> node_elem(nn);
+  for (int e = 0; e < K; e++)
+    for (int p = L->off[e]; p < L->off[e + 1]; p++) node_elem[p] = e;
+
+  DevArena& A = L->arena;
+  L->d_ord = A.upload(ord);
+  L->d_off = A.upload(L->off);
+  L->d_fo = A.upload(L->fo);
+  L->d_node_elem = A.upload(node_elem);
+  L->d_elist = A.upload(elist);
+  L->d_tiles = A.upload(tiles);
+  L->d_faces = A.upload(faces);
+  L->d_mface = A.upload(mface);
+  L->d_ftile = A.upload(ftile);
+  L->d_Ja = A.alloc<double>(9 * nn);
+  L->d_invJ = A.alloc<double>(nn);
+  L->d_J = A.alloc<double>(nn);
+  L->d_Nout = A.alloc<double>(3 * nf);
+  L->d_mgeo = A.alloc<double>(4 * (size_t)std::max(L->nm, 1));
+  L->d_qf = A.alloc<double>(5 * nf);
+  L->d_Ws = A.alloc<double>(4 * nf);
+  L->d_gW = A.alloc<double>(12 * nn);
+  L->d_gf = A.alloc<double>(12 * nf);
+  L->d_PhiA = A.alloc<double>(5 * nf);
+  L->d_Phi = A.alloc<double>(5 * nf);
+
+  LevelDev& D = L->dev;
+  D.K = K; D.nn = (int)nn; D.nf = (int)nf; D.nm = L->nm; D.fam = L->fam;
+  D.ord = L->d_ord; D.off = L->d_off; D.fo = L->d_fo;
+  D.Ja = L->d_Ja; D.invJ = L->d_invJ; D.J = L->d_J; D.Nout = L->d_Nout;
+  D.tiles = L->d_tiles; D.elist = L->d_elist;
+  D.faces = L->d_faces; D.mface = L->d_mface; D.ftile = L->d_ftile; D.mgeo = L->d_mgeo;
+  D.T = s->ctx->T[L->fam];
+
+  // geometry on the device
+  DevArena tmp;
+  GeoArgs G;
+  G.gnodes = m->d_gnodes;
+  G.M1 = m->M[0]; G.M2 = m->M[1]; G.M3 = m->M[2];
+  G.node_elem = L->d_node_elem;
+  G.X = tmp.alloc<double>(3 * nn);
+  G.dX = tmp.alloc<double>(9 * nn);
+  G.Ja = L->d_Ja; G.invJ = L->d_invJ; G.J = L->d_J;
+  int nb = cdiv(nn, 256);
+  k_geo_x<<<nb, 256>>>(D, G);
+  k_geo_dx<<<nb, 256>>>(D, G);
+  k_geo_metric<<<nb, 256>>>(D, G);
+  k_geo_faces<<<L->ntiles, PMG_BLOCK>>>(D, L->d_Nout);
+  if (L->nm > 0) k_mortar_geo<<<cdiv(L->nm, 256), 256>>>(D, L->d_mgeo);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipDeviceSynchronize());
+  return L;
+}
+
+static std::unique_ptr<XferTiles> build_xfer(const Level& fine, const Level& coarse) {
+  auto X = std::make_unique<XferTiles>();
+  std::map<std::pair<int, int>, std::vector<int>> buckets;
+  for (int e = 0; e < fine.K; e++) {
+    int a = pack3(fine.ord[3 * e] + 1, fine.ord[3 * e + 1] + 1, fine.ord[3 * e + 2] + 1);
+    int b = pack3(coarse.ord[3 * e] + 1, coarse.ord[3 * e + 1] + 1, coarse.ord[3 * e + 2] + 1);
+    buckets[{a, b}].push_back(e);
+  }
+  std::vector<int> elist;
+  std::vector<int4> tr, tp;
+  int stride = 1;
+  for (auto& kv : buckets) {
+    int a = kv.first.first, b = kv.first.second;
+    int na = (a & 255) * ((a >> 8) & 255) * (a >> 16);
+    int nb = (b & 255) * ((b >> 8) & 255) * (b >> 16);
+    int big = std::max(na, nb);
+    int per = std::max(1, TILE_TARGET / big);
+    const auto& es = kv.second;
+    for (size_t i = 0; i < es.size(); i += per) {
+      int cnt = (int)std::min<size_t>(per, es.size() - i);
+      tr.push_back(make_int4((int)elist.size(), cnt, a, b));
+      tp.push_back(make_int4((int)elist.size(), cnt, b, a));
+      stride = std::max(stride, cnt * big);
+      for (int c = 0; c < cnt; c++) elist.push_back(es[i + c]);
+    }
+  }
+  X->ntiles = (int)tr.size();
+  X->lds_stride = stride;
+  X->d_restrict = X->arena.upload(tr);
+  X->d_prolong = X->arena.upload(tp);
+  X->d_elist = X->arena.upload(elist);
+  return X;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Operator, smoother, transfers
+// ------------------------------------------------------------------------------------------------
+static DivArgs div_args(int mode) {
+  DivArgs a;
+  memset(&a, 0, sizeof(a));
+  a.mode = mode;
+  return a;
+}
+
+// A(Q) through the five stages: q traces, interface state, gradient, gradient traces, numerical flux,
+// divergence (the epilogue in 'a' decides what is written).
+static void op_eval(const pmg_solver_s* s, Level& L, const double* Q, bool isolated, const DivArgs& a,
+                    hipStream_t st) {
+  const LevelDev& D = L.dev;
+  k_trace<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, 5, L.d_qf);
+  if (isolated) k_face1_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_Phi);
+  else k_face1<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_PhiA);
+  k_grad<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, s->phys, Q, L.d_Ws, L.d_gW);
+  k_trace<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, L.d_gW, 12, L.d_gf);
+  if (isolated) k_face2_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_Phi);
+  else k_face2<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_PhiA, L.d_Phi);
+  k_div<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(D, s->phys, Q, L.d_gW, L.d_Phi, a);
+}
+
+static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+static const double RK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+enum { SLOT_DT = 0, SLOT_NORM = 1, SLOT_NORM2 = 2, NSLOTS = 4 };
+
+static void reset_slot(const pmg_solver_s* s, int slot, double v, hipStream_t st) {
+  unsigned long long bits;
+  memcpy(&bits, &v, sizeof(bits));
+  k_fill_u64<<<1, 64, 0, st>>>(s->d_red + slot, 1, bits);
+}
+
+static double read_slot(const pmg_solver_s* s, int slot, hipStream_t st) {
+  unsigned long long bits;
+  HIPCHECK(hipMemcpyAsync(&bits, s->d_red + slot, sizeof(bits), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  HIPCHECK(hipGetLastError());
+  double v;
+  memcpy(&v, &bits, sizeof(v));
+  return v;
+}
+
+static void timestep(const pmg_solver_s* s, Level& L, const double* Q, hipStream_t st) {
+  reset_slot(s, SLOT_DT, INFINITY, st);
+  k_dt<<<L.ntiles, PMG_BLOCK, 0, st>>>(L.dev, s->phys, Q, s->d_red + SLOT_DT);
+}
+
+static void smooth(const pmg_solver_s* s, Level& L, double* Q, const double* S, double* G, int sweeps,
+                   hipStream_t st) {
+  for (int it = 0; it < sweeps; it++) {
+    timestep(s, L, Q, st);
+    for (int k = 0; k < 3; k++) {
+      DivArgs a = div_args(EPI_RK);
+      a.S = S;
+      a.Qrk = Q;
+      a.G = G;
+      a.dt = (const double*)(s->d_red + SLOT_DT);
+      a.a = RK_A[k];
+      a.b = RK_B[k];
+      op_eval(s, L, Q, false, a, st);
+    }
+  }
+}
+
+// out = S - A(Q); optional max-norm into a slot
+static void residual(const pmg_solver_s* s, Level& L, const double* Q, const double* S, double* out, bool isolated,
+                     int norm_slot, hipStream_t st) {
+  DivArgs a = div_args(EPI_R);
+  a.S = S;
+  a.out = out;
+  if (norm_slot >= 0) {
+    reset_slot(s, norm_slot, 0.0, st);
+    a.norm = s->d_red + norm_slot;
+  }
+  op_eval(s, L, Q, isolated, a, st);
+}
+
+static void xfer(const Level& from, const Level& to, const XferTiles& X, bool prolong, const double* U,
+                 const double* U0, double* V, bool accumulate, hipStream_t st) {
+  XferArgs a;
+  a.tiles = prolong ? X.d_prolong : X.d_restrict;
+  a.elist = X.d_elist;
+  a.off_from = from.d_off;
+  a.off_to = to.d_off;
+  a.nn_from = from.nn;
+  a.nn_to = to.nn;
+  a.T = from.dev.T;
+  a.U = U;
+  a.U0 = U0;
+  a.V = V;
+  a.accumulate = accumulate ? 1 : 0;
+  a.lds_stride = X.lds_stride;
+  k_transfer<<<X.ntiles, PMG_BLOCK, (size_t)10 * X.lds_stride * sizeof(double), st>>>(a);
+}
+
+static void copy(double* dst, const double* src, size_t n, hipStream_t st) {
+  k_copy<<<cdiv(n, 256), 256, 0, st>>>(dst, src, n);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Hierarchies and the FAS V-cycle (Sec. 3.1, Algorithm "FAS: V-Cycle"; Sec. 3.2.3 anisotropic cycle)
+// ------------------------------------------------------------------------------------------------
+static void build_hier(pmg_solver_s* s, Hier& H, int dir, const std::vector<int>& caps_finest_first) {
+  H.dir = dir;
+  const int nlev = (int)caps_finest_first.size();
+  const int K = (int)s->mesh->K;
+  H.lv.resize(nlev);
+  H.caps.resize(nlev);
+  for (int l = 0; l < nlev; l++) {
+    int cap = caps_finest_first[nlev - 1 - l];
+    H.caps[l] = cap;
+    if (l == nlev - 1) {
+      H.lv[l] = s->top;
+      continue;
+    }
+    std::vector<int> o(3 * K);
+    for (int e = 0; e < K; e++)
+      for (int d = 0; d < 3; d++) {
+        int p = s->orders[3 * e + d];
+        o[3 * e + d] = ((dir < 0 || dir == d) && p > cap) ? cap : p;
+      }
+    H.lv[l] = build_level(s, o);
+  }
+  H.Q.assign(nlev, nullptr); H.Q0.assign(nlev, nullptr); H.S.assign(nlev, nullptr); H.r.assign(nlev, nullptr);
+  H.Sp.assign(nlev, nullptr); H.G.assign(nlev, nullptr); H.R.assign(nlev, nullptr);
+  for (int l = 0; l < nlev; l++) {
+    size_t n = 5 * (size_t)H.lv[l]->nn;
+    if (l < nlev - 1) H.Q[l] = H.arena.alloc<double>(n);  // the top state is the caller's buffer
+    H.Q0[l] = H.arena.alloc<double>(n);
+    H.S[l] = H.arena.alloc<double>(n);
+    H.r[l] = H.arena.alloc<double>(n);
+    H.Sp[l] = H.arena.alloc<double>(n);
+    H.G[l] = H.arena.alloc<double>(n);
+    H.R[l] = H.arena.alloc<double>(n);
+  }
+  H.xf.clear();
+  for (int l = 0; l + 1 < nlev; l++) H.xf.push_back(build_xfer(*H.lv[l + 1], *H.lv[l]));
+}
+
+struct TauRec {
+  double* map;
+  int nt;
+  int isolated;
+};
+
+struct CycleCtx {
+  pmg_solver_s* s;
+  Hier* H;
+  hipStream_t st;
+  const TauRec* tau;
+};
+
+static void restrict_to(CycleCtx& c, int l, const double* Uf, double* Uc) {
+  Hier& H = *c.H;
+  xfer(*H.lv[l], *H.lv[l - 1], *H.xf[l - 1], false, Uf, nullptr, Uc, false, c.st);
+}
+
+static void absmax(CycleCtx& c, const double* U, size_t n, int slot) {
+  reset_slot(c.s, slot, 0.0, c.st);
+  k_absmax<<<std::min(cdiv(n, 256), 2048), 256, 0, c.st>>>(U, n, c.s->d_red + slot);
+}
+
+// pre-smoothing; leaves R[l] = S - A(Q) and returns ||R||_inf when tuning (else 0)
+static double pre_smooth(CycleCtx& c, int l, int top) {
+  pmg_solver_s* s = c.s;
+  Hier& H = *c.H;
+  Level& L = *H.lv[l];
+  const pmg_mg_params& P = s->mg;
+  if (l == 0) {
+    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_coarse, c.st);
+    return 0.0;
+  }
+  if (!P.tuning) {
+    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_pre, c.st);
+    residual(s, L, H.Q[l], H.S[l], H.R[l], false, -1, c.st);
+    return 0.0;
+  }
+  double rf = 0.0;
+  for (int rep = 0; rep < std::max(1, P.max_repeats); rep++) {
+    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_pre, c.st);
+    residual(s, L, H.Q[l], H.S[l], H.R[l], false, SLOT_NORM, c.st);
+    restrict_to(c, l, H.R[l], H.r[l - 1]);
+    absmax(c, H.r[l - 1], 5 * (size_t)H.lv[l - 1]->nn, SLOT_NORM2);
+    rf = read_slot(s, SLOT_NORM, c.st);
+    double rc = read_slot(s, SLOT_NORM2, c.st);
+    if (rf != rf) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual during pre-smoothing");
+    if (rf < P.eta * rc) break;
+  }
+  return rf;
+}
+
+static void post_smooth(CycleCtx& c, int l, double rpre) {
+  pmg_solver_s* s = c.s;
+  Hier& H = *c.H;
+  Level& L = *H.lv[l];
+  const pmg_mg_params& P = s->mg;
+  if (!P.tuning) {
+    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_post, c.st);
+    return;
+  }
+  for (int rep = 0; rep < std::max(1, P.max_repeats); rep++) {
+    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_post, c.st);
+    residual(s, L, H.Q[l], H.S[l], H.R[l], false, SLOT_NORM, c.st);
+    double r = read_slot(s, SLOT_NORM, c.st);
+    if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual during post-smoothing");
+    if (r <= rpre) break;
+  }
+}
+
+static void vcycle_rec(CycleCtx& c, int l, int top) {
+  pmg_solver_s* s = c.s;
+  Hier& H = *c.H;
+  Level& L = *H.lv[l];
+  const size_t n = 5 * (size_t)L.nn;
+  if (l < top) {
+    // coarse source S = A(Q~) + r (eq. FAScoarseSource); truncation error from the same evaluation
+    DivArgs a = div_args(EPI_SRC);
+    a.S = H.r[l];
+    a.out = H.S[l];
+    const bool rec = c.tau != nullptr;
+    if (rec && !c.tau->isolated) {
+      a.Sphys = H.Sp[l];
+      a.tau_map = c.tau->map;
+      a.tau_dir = H.dir;
+      a.tau_cap = H.caps[l];
+      a.tau_nt = c.tau->nt;
+      a.tau_top_ord = s->top->d_ord;
+    }
+    op_eval(s, L, H.Q[l], false, a, c.st);
+    if (rec && c.tau->isolated) {
+      DivArgs t = div_args(EPI_TAU);
+      t.Sphys = H.Sp[l];
+      t.tau_map = c.tau->map;
+      t.tau_dir = H.dir;
+      t.tau_cap = H.caps[l];
+      t.tau_nt = c.tau->nt;
+      t.tau_top_ord = s->top->d_ord;
+      op_eval(s, L, H.Q[l], true, t, c.st);
+    }
+  }
+  copy(H.Q0[l], H.Q[l], n, c.st);
+  double rpre = pre_smooth(c, l, top);
+  if (l > 0) {
+    Level& Lc = *H.lv[l - 1];
+    xfer(L, Lc, *H.xf[l - 1], false, H.Q[l], nullptr, H.Q[l - 1], false, c.st);
+    if (!s->mg.tuning) xfer(L, Lc, *H.xf[l - 1], false, H.R[l], nullptr, H.r[l - 1], false, c.st);
+    vcycle_rec(c, l - 1, top);
+    // Q <- Q + I (Q~c - Q~c_0)   (eqs. FASIterError, FASCorrectSol)
+    xfer(Lc, L, *H.xf[l - 1], true, H.Q[l - 1], H.Q0[l - 1], H.Q[l], true, c.st);
+    post_smooth(c, l, rpre);
+  }
+}
+
+// physical source on every level: the top one as given (zero when absent), restricted level by level
+static void set_sources(CycleCtx& c, const double* S) {
+  Hier& H = *c.H;
+  int top = H.top();
+  size_t n = 5 * (size_t)H.lv[top]->nn;
+  copy(H.Sp[top], S ? S : c.s->d_zero, n, c.st);
+  for (int l = top; l > 0; l--) restrict_to(c, l, H.Sp[l], H.Sp[l - 1]);
+}
+
+static void run_vcycles(pmg_solver_s* s, Hier& H, double* Q, const double* S, int ncycles, const TauRec* tau,
+                        hipStream_t st) {
+  CycleCtx c{s, &H, st, tau};
+  int top = H.top();
+  H.Q[top] = Q;
+  set_sources(c, S);
+  copy(H.S[top], H.Sp[top], 5 * (size_t)H.lv[top]->nn, st);
+  for (int k = 0; k < ncycles; k++) vcycle_rec(c, top, top);
+  H.Q[top] = nullptr;
+}
+
+static Hier& aniso_hier(pmg_solver_s* s, int d) {
+  if (!s->aniso[d]) {
+    int pmax = 1;
+    for (size_t e = 0; e < s->mesh->K; e++) pmax = std::max(pmax, s->orders[3 * e + d]);
+    std::vector<int> caps;
+    for (int c = pmax; c >= 1; c--) caps.push_back(c);
+    s->aniso[d] = std::make_unique<Hier>();
+    build_hier(s, *s->aniso[d], d, caps);
+  }
+  return *s->aniso[d];
+}
+
+// ------------------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* pmg_last_error(void) { return g_err.c_str(); }
+
+pmg_status pmg_ctx_create(int hip_device, pmg_ctx* out) {
+  return guard([&] {
+    REQUIRE(out, "out is NULL");
+    int n = 0;
+    HIPCHECK(hipGetDeviceCount(&n));
+    REQUIRE(hip_device >= 0 && hip_device < n, "no such HIP device");
+    HIPCHECK(hipSetDevice(hip_device));
+    auto c = std::make_unique<pmg_ctx_s>();
+    c->device = hip_device;
+    BasisTables B[2];
+    std::vector<double> T(TMAT_STRIDE);
+    for (int fam = 0; fam < 2; fam++) {
+      hb::build_family(fam, B[fam], T.data());
+      c->T[fam] = c->arena.upload(T);
+    }
+    HIPCHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_tab), B, sizeof(B)));
+    *out = c.release();
+  });
+}
+
+void pmg_ctx_destroy(pmg_ctx ctx) { delete ctx; }
+
+pmg_status pmg_mesh_create(pmg_ctx ctx, int64_t K, const int32_t M[3], const double* geom_nodes,
+                           const int64_t* nbr_elem, const int32_t* nbr_face, const int32_t* orient,
+                           const int32_t* bc, pmg_mesh* out) {
+  return guard([&] {
+    REQUIRE(ctx && out && M && geom_nodes && nbr_elem && nbr_face && orient && bc, "NULL argument");
+    REQUIRE(K > 0 && K < (1 << 30), "K out of range");
+    for (int d = 0; d < 3; d++) REQUIRE(M[d] >= 1 && M[d] <= 4, "mapping order must be 1..4");
+    for (int64_t e = 0; e < K; e++)
+      for (int f = 0; f < 6; f++) {
+        int64_t g = nbr_elem[6 * e + f];
+        if (g < 0) {
+          REQUIRE(bc[6 * e + f] >= 1 && bc[6 * e + f] <= 3, "boundary face without a boundary tag");
+          continue;
+        }
+        REQUIRE(g < K, "neighbour index out of range");
+        int h = nbr_face[6 * e + f];
+        REQUIRE(h >= 0 && h < 6, "neighbour face out of range");
+        REQUIRE(orient[6 * e + f] >= 0 && orient[6 * e + f] < 8, "orientation code out of range");
+        REQUIRE(nbr_elem[6 * g + h] == e && nbr_face[6 * g + h] == f, "neighbour does not point back");
+        REQUIRE((h / 2 == f / 2) || true, "");
+      }
+    HIPCHECK(hipSetDevice(ctx->device));
+    auto m = std::make_unique<pmg_mesh_s>();
+    m->ctx = ctx;
+    m->K = K;
+    for (int d = 0; d < 3; d++) m->M[d] = M[d];
+    size_t ng = (size_t)K * (M[0] + 1) * (M[1] + 1) * (M[2] + 1) * 3;
+    m->gnodes.assign(geom_nodes, geom_nodes + ng);
+    m->nbr.assign(nbr_elem, nbr_elem + 6 * K);
+    m->nbrf.assign(nbr_face, nbr_face + 6 * K);
+    m->orient.assign(orient, orient + 6 * K);
+    m->bc.assign(bc, bc + 6 * K);
+    m->d_gnodes = m->arena.upload(m->gnodes);
+    *out = m.release();
+  });
+}
+
+void pmg_mesh_destroy(pmg_mesh mesh) { delete mesh; }
+
+pmg_status pmg_solver_create(pmg_ctx ctx, pmg_mesh mesh, const int32_t* orders, const pmg_physics* ph,
+                             const pmg_mg_params* mg, pmg_solver* out) {
+  return guard([&] {
+    REQUIRE(ctx && mesh && orders && ph && out, "NULL argument");
+    REQUIRE(mesh->ctx == ctx, "mesh belongs to another context");
+    REQUIRE(ph->node_family == 0 || ph->node_family == 1, "node_family must be 0 or 1");
+    REQUIRE(ph->mach > 0 && ph->reynolds > 0 && ph->gamma > 1 && ph->prandtl > 0, "bad physics parameters");
+    HIPCHECK(hipSetDevice(ctx->device));
+    auto s = std::make_unique<pmg_solver_s>();
+    s->ctx = ctx;
+    s->mesh = mesh;
+    const int K = (int)mesh->K;
+    s->orders.assign(orders, orders + 3 * K);
+    for (int v : s->orders) REQUIRE(v >= 1 && v <= PMG_MAXN - 1, "orders must be 1..7");
+    for (int v : s->orders) s->nmax = std::max(s->nmax, v);
+    Phys& P = s->phys;
+    P.gamma = ph->gamma;
+    P.gm1 = ph->gamma - 1.0;
+    P.gM2 = ph->gamma * ph->mach * ph->mach;
+    P.Re = ph->reynolds;
+    P.invRe = 1.0 / ph->reynolds;
+    P.kcoef = 1.0 / ((ph->gamma - 1.0) * ph->prandtl * ph->mach * ph->mach);
+    P.suth = ph->sutherland;
+    P.suth1 = 1.0 + ph->sutherland;
+    P.cfl_adv = ph->cfl_adv;
+    P.cfl_visc = ph->cfl_visc;
+    P.pinf = 1.0 / (ph->gamma * ph->mach * ph->mach);
+    P.rhoE_inf = P.pinf / (ph->gamma - 1.0) + 0.5;
+    P.visc_const = ph->viscosity_model == 1;
+    P.family = ph->node_family;
+    pmg_mg_params d;
+    memset(&d, 0, sizeof(d));
+    d.beta_pre = d.beta_post = d.beta_coarse = 3;
+    d.eta = 1.1;
+    d.max_repeats = 10;
+    d.fmg_threshold = 0.1;
+    s->mg = mg ? *mg : d;
+    REQUIRE(s->mg.beta_pre >= 0 && s->mg.beta_post >= 0 && s->mg.beta_coarse >= 0, "negative sweep count");
+    s->top = build_level(s.get(), s->orders);
+    std::vector<int> caps;
+    if (mg && mg->n_levels > 0 && mg->level_caps) {
+      caps.assign(mg->level_caps, mg->level_caps + mg->n_levels);
+      for (size_t i = 1; i < caps.size(); i++) REQUIRE(caps[i] < caps[i - 1] && caps[i] >= 1, "level caps must decrease");
+    } else {
+      int nl = (mg && mg->n_levels > 0) ? mg->n_levels : s->nmax;
+      for (int c = s->nmax; c >= 1 && (int)caps.size() < nl; c--) caps.push_back(c);
+    }
+    s->mg.level_caps = nullptr;
+    build_hier(s.get(), s->iso, -1, caps);
+    size_t n = 5 * (size_t)s->top->nn;
+    s->d_red = s->arena.alloc<unsigned long long>(NSLOTS);
+    s->d_zero = s->arena.alloc<double>(n);
+    s->d_R = s->arena.alloc<double>(n);
+    s->d_G = s->arena.alloc<double>(n);
+    HIPCHECK(hipMemset(s->d_zero, 0, n * sizeof(double)));
+    HIPCHECK(hipDeviceSynchronize());
+    *out = s.release();
+  });
+}
+
+void pmg_solver_destroy(pmg_solver s) { delete s; }
+
+pmg_status pmg_state_layout(pmg_solver s, int64_t* n_nodes, int64_t* elem_node_offset) {
+  return guard([&] {
+    REQUIRE(s, "NULL solver");
+    if (n_nodes) *n_nodes = s->top->nn;
+    if (elem_node_offset)
+      for (int e = 0; e <= s->top->K; e++) elem_node_offset[e] = s->top->off[e];
+  });
+}
+
+pmg_status pmg_init_freestream(pmg_solver s, double* Q_dev, void* stream) {
+  return guard([&] {
+    REQUIRE(s && Q_dev, "NULL argument");
+    k_freestream<<<cdiv(s->top->nn, 256), 256, 0, (hipStream_t)stream>>>(s->phys, Q_dev, s->top->nn);
+    HIPCHECK(hipGetLastError());
+  });
+}
+
+pmg_status pmg_residual(pmg_solver s, int op, const double* Q_dev, const double* S_dev, double* R_dev,
+                        double* res_inf_host, void* stream) {
+  return guard([&] {
+    REQUIRE(s && Q_dev && R_dev, "NULL argument");
+    REQUIRE(op == 0 || op == 1, "op must be 0 (DG) or 1 (isolated)");
+    hipStream_t st = (hipStream_t)stream;
+    residual(s, *s->top, Q_dev, S_dev, R_dev, op == 1, res_inf_host ? SLOT_NORM : -1, st);
+    HIPCHECK(hipGetLastError());
+    if (res_inf_host) {
+      *res_inf_host = read_slot(s, SLOT_NORM, st);
+      if (*res_inf_host != *res_inf_host) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
+    }
+  });
+}
+
+pmg_status pmg_timestep(pmg_solver s, const double* Q_dev, double* dt_host, void* stream) {
+  return guard([&] {
+    REQUIRE(s && Q_dev && dt_host, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    timestep(s, *s->top, Q_dev, st);
+    *dt_host = read_slot(s, SLOT_DT, st);
+  });
+}
+
+pmg_status pmg_smooth(pmg_solver s, double* Q_dev, const double* S_dev, int sweeps, void* stream) {
+  return guard([&] {
+    REQUIRE(s && Q_dev && sweeps >= 0, "bad argument");
+    smooth(s, *s->top, Q_dev, S_dev, s->d_G, sweeps, (hipStream_t)stream);
+    HIPCHECK(hipGetLastError());
+  });
+}
+
+static Hier& pick_hier(pmg_solver s, int hierarchy) {
+  REQUIRE(hierarchy >= -1 && hierarchy <= 2, "hierarchy must be -1, 0, 1 or 2");
+  return hierarchy < 0 ? s->iso : aniso_hier(s, hierarchy);
+}
+
+pmg_status pmg_level_info(pmg_solver s, int hierarchy, int level, int32_t* n_levels, int64_t* n_nodes,
+                          int32_t* orders) {
+  return guard([&] {
+    REQUIRE(s, "NULL solver");
+    Hier& H = pick_hier(s, hierarchy);
+    if (n_levels) *n_levels = (int32_t)H.lv.size();
+    if (level < 0) return;
+    REQUIRE(level < (int)H.lv.size(), "level out of range");
+    if (n_nodes) *n_nodes = H.lv[level]->nn;
+    if (orders) memcpy(orders, H.lv[level]->ord.data(), sizeof(int32_t) * 3 * s->mesh->K);
+  });
+}
+
+pmg_status pmg_restrict(pmg_solver s, int hierarchy, int level, const double* Uf, double* Uc, void* stream) {
+  return guard([&] {
+    REQUIRE(s && Uf && Uc, "NULL argument");
+    Hier& H = pick_hier(s, hierarchy);
+    REQUIRE(level >= 1 && level < (int)H.lv.size(), "level out of range");
+    xfer(*H.lv[level], *H.lv[level - 1], *H.xf[level - 1], false, Uf, nullptr, Uc, false, (hipStream_t)stream);
+    HIPCHECK(hipGetLastError());
+  });
+}
+
+pmg_status pmg_prolong(pmg_solver s, int hierarchy, int level, const double* Uc, double* Uf, void* stream) {
+  return guard([&] {
+    REQUIRE(s && Uf && Uc, "NULL argument");
+    Hier& H = pick_hier(s, hierarchy);
+    REQUIRE(level >= 0 && level + 1 < (int)H.lv.size(), "level out of range");
+    xfer(*H.lv[level], *H.lv[level + 1], *H.xf[level], true, Uc, nullptr, Uf, false, (hipStream_t)stream);
+    HIPCHECK(hipGetLastError());
+  });
+}
+
+pmg_status pmg_vcycle(pmg_solver s, double* Q_dev, const double* S_dev, int n_cycles, double* res_inf_host,
+                      void* stream) {
+  return guard([&] {
+    REQUIRE(s && Q_dev && n_cycles >= 0, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    run_vcycles(s, s->iso, Q_dev, S_dev, n_cycles, nullptr, st);
+    HIPCHECK(hipGetLastError());
+    if (res_inf_host) {
+      residual(s, *s->top, Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
+      *res_inf_host = read_slot(s, SLOT_NORM, st);
+      if (*res_inf_host != *res_inf_host) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
+    }
+  });
+}
+
+pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double tol, int max_cycles, int* cycles_out,
+                     double* res_inf_out, void* stream) {
+  pmg_status rc = guard([&] {
+    REQUIRE(s && Q_dev && max_cycles >= 0, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    Hier& H = s->iso;
+    CycleCtx c{s, &H, st, nullptr};
+    const int top = H.top();
+    H.Q[top] = Q_dev;
+    set_sources(c, S_dev);
+    int cycles = 0;
+    double r = 0.0;
+    if (s->mg.fmg) {
+      for (int l = top; l > 0; l--) restrict_to(c, l, H.Q[l], H.Q[l - 1]);
+      for (int l = 0; l < top; l++) {
+        Level& L = *H.lv[l];
+        copy(H.S[l], H.Sp[l], 5 * (size_t)L.nn, st);
+        for (;;) {
+          residual(s, L, H.Q[l], H.Sp[l], H.R[l], false, SLOT_NORM, st);
+          r = read_slot(s, SLOT_NORM, st);
+          if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual in the FMG start");
+          if (r < s->mg.fmg_threshold || cycles >= max_cycles) break;
+          vcycle_rec(c, l, l);
+          cycles++;
+        }
+        xfer(L, *H.lv[l + 1], *H.xf[l], true, H.Q[l], nullptr, H.Q[l + 1], false, st);
+      }
+    }
+    copy(H.S[top], H.Sp[top], 5 * (size_t)H.lv[top]->nn, st);
+    for (;;) {
+      residual(s, *H.lv[top], Q_dev, H.Sp[top], s->d_R, false, SLOT_NORM, st);
+      r = read_slot(s, SLOT_NORM, st);
+      if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
+      if (r < tol || cycles >= max_cycles) break;
+      vcycle_rec(c, top, top);
+      cycles++;
+    }
+    H.Q[top] = nullptr;
+    if (cycles_out) *cycles_out = cycles;
+    if (res_inf_out) *res_inf_out = r;
+    if (r >= tol) throw PmgError(PMG_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance");
+  });
+  if (s) s->iso.Q[s->iso.top()] = nullptr;
+  return rc;
+}
+
+pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, int isolated, double* tau_map_dev,
+                            void* stream) {
+  return guard([&] {
+    REQUIRE(s && Q_dev && tau_map_dev, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int nt = std::max(s->nmax - 1, 1);
+    size_t n = (size_t)s->mesh->K * 3 * nt;
+    k_fill<<<cdiv(n, 256), 256, 0, st>>>(tau_map_dev, n, NAN);
+    TauRec tau{tau_map_dev, nt, isolated ? 1 : 0};
+    for (int d = 0; d < 3; d++) {
+      Hier& H = aniso_hier(s, d);
+      if (H.lv.size() < 2) continue;
+      run_vcycles(s, H, Q_dev, S_dev, 1, &tau, st);
+    }
+    HIPCHECK(hipGetLastError());
+  });
+}
+
+}  // extern "C"

@@ -486,13 +486,14 @@ def config_plate(nx: int = 64, ny: int = 32, N=(6, 6, 1), seed: int = 2, amp: fl
     return Workload(f"plate{nx}x{ny}_N{N[0]}{N[1]}{N[2]}", mesh, orders, phys, Q)
 
 
-def config_ogrid(nt: int = 8, nr: int = 13, seed: int = 3, lo: int = 1, hi: int = 7, amp: float = 1e-3) -> Workload:
+def config_ogrid(nt: int = 8, nr: int = 13, seed: int = 3, lo: int = 1, hi: int = 7, amp: float = 1e-3,
+                 r_out: float = 20.0, ratio: float = 1.25, cfl: float = 0.2) -> Workload:
     """Six-block O-grid around the unit sphere (outer radius 20), quadratic mapping, iid orders in [lo,hi].
     Element frames are rotated with a seed, as a mesh generator would leave them, so the faces carry every
-    orientation code."""
-    mesh, _ = reorient(ogrid_mesh(nt, nr), seed)
+    orientation code.  Random low orders on curved elements need a smaller explicit step constant."""
+    mesh, _ = reorient(ogrid_mesh(nt, nr, r_out=r_out, ratio=ratio), seed)
     orders = random_orders(mesh.K, lo, hi, seed)
-    phys = Physics(mach=0.2, reynolds=200.0, family=FAMILY_LG)
+    phys = Physics(mach=0.2, reynolds=200.0, family=FAMILY_LG, cfl_adv=cfl, cfl_visc=cfl)
     n_nodes = int(node_offsets(orders)[-1])
     Q = perturbed_freestream(n_nodes, phys.mach, amp, seed + 100)
     return Workload(f"ogrid{nt}x{nr}", mesh, orders, phys, Q)

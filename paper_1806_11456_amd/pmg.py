@@ -1,0 +1,259 @@
+"""Thin Python binding of the pmg C-ABI (include/pmg.h): argument marshalling only.
+
+Device arrays are torch tensors on the solver's GPU (float64, contiguous, shape (5, n_nodes) for states);
+every call is enqueued on torch's current stream.  All computation happens in the HIP library; if it is
+not built this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmg.so")
+
+STATUS = {0: "PMG_OK", 1: "PMG_ERR_INVALID_ARG", 2: "PMG_ERR_OOM", 3: "PMG_ERR_HIP", 4: "PMG_ERR_NONPHYSICAL",
+          5: "PMG_ERR_NOT_CONVERGED", 6: "PMG_ERR_BUSY", 7: "PMG_ERR_UNIMPLEMENTED"}
+
+# every entry point the header declares (checked by the CPU test suite)
+EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_create", "pmg_mesh_destroy",
+           "pmg_solver_create", "pmg_solver_destroy", "pmg_state_layout", "pmg_init_freestream", "pmg_residual",
+           "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
+           "pmg_solve", "pmg_tau_estimate"]
+
+
+class PmgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Physics(C.Structure):
+    _fields_ = [("mach", C.c_double), ("reynolds", C.c_double), ("prandtl", C.c_double), ("gamma", C.c_double),
+                ("sutherland", C.c_double), ("cfl_adv", C.c_double), ("cfl_visc", C.c_double),
+                ("node_family", C.c_int32), ("viscosity_model", C.c_int32)]
+
+
+class MGParams(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("level_caps", C.POINTER(C.c_int32)), ("beta_pre", C.c_int32),
+                ("beta_post", C.c_int32), ("beta_coarse", C.c_int32), ("tuning", C.c_int32), ("eta", C.c_double),
+                ("max_repeats", C.c_int32), ("fmg", C.c_int32), ("fmg_threshold", C.c_double)]
+
+
+@dataclasses.dataclass
+class MG:
+    level_caps: Optional[Sequence[int]] = None
+    beta_pre: int = 3
+    beta_post: int = 3
+    beta_coarse: int = 3
+    tuning: int = 0
+    eta: float = 1.1
+    max_repeats: int = 10
+    fmg: int = 0
+    fmg_threshold: float = 0.1
+
+
+_lib = None
+
+
+def lib():
+    """Load libpmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1806_11456_amd/build.py "
+                           "(or __graft_entry__.build()); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    P, D, I32, I64, V = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_void_p
+    pp = C.POINTER(C.c_void_p)
+    L.pmg_last_error.restype = C.c_char_p
+    L.pmg_ctx_create.argtypes = [C.c_int, pp]
+    L.pmg_ctx_destroy.argtypes = [P]
+    L.pmg_mesh_create.argtypes = [P, C.c_int64, I32, D, I64, I32, I32, I32, pp]
+    L.pmg_mesh_destroy.argtypes = [P]
+    L.pmg_solver_create.argtypes = [P, P, I32, C.POINTER(Physics), C.POINTER(MGParams), pp]
+    L.pmg_solver_destroy.argtypes = [P]
+    L.pmg_state_layout.argtypes = [P, I64, I64]
+    L.pmg_init_freestream.argtypes = [P, V, V]
+    L.pmg_residual.argtypes = [P, C.c_int, V, V, V, D, V]
+    L.pmg_timestep.argtypes = [P, V, D, V]
+    L.pmg_smooth.argtypes = [P, V, V, C.c_int, V]
+    L.pmg_level_info.argtypes = [P, C.c_int, C.c_int, I32, I64, I32]
+    L.pmg_restrict.argtypes = [P, C.c_int, C.c_int, V, V, V]
+    L.pmg_prolong.argtypes = [P, C.c_int, C.c_int, V, V, V]
+    L.pmg_vcycle.argtypes = [P, V, V, C.c_int, D, V]
+    L.pmg_solve.argtypes = [P, V, V, C.c_double, C.c_int, I32, D, V]
+    L.pmg_tau_estimate.argtypes = [P, V, V, C.c_int, V, V]
+    for name in EXPORTS:
+        if name not in ("pmg_last_error", "pmg_ctx_destroy", "pmg_mesh_destroy", "pmg_solver_destroy"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PmgError(rc, lib().pmg_last_error().decode())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype.is_floating_point and t.is_contiguous(), "expected a contiguous CUDA tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().pmg_ctx_create(device, C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pmg_ctx_destroy(self.h)
+            self.h = None
+
+
+class Mesh:
+    def __init__(self, ctx: Context, mesh):
+        self.ctx = ctx
+        self.K = int(mesh.K)
+        M = np.asarray(mesh.M, dtype=np.int32)
+        self._arrs = [np.ascontiguousarray(mesh.gnodes, dtype=np.float64), np.ascontiguousarray(mesh.nbr_elem, dtype=np.int64),
+                      np.ascontiguousarray(mesh.nbr_face, dtype=np.int32), np.ascontiguousarray(mesh.orient, dtype=np.int32),
+                      np.ascontiguousarray(mesh.bc, dtype=np.int32)]
+        g, nb, nf, o, bc = self._arrs
+        h = C.c_void_p()
+        _check(lib().pmg_mesh_create(ctx.h, self.K, M.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     g.ctypes.data_as(C.POINTER(C.c_double)), nb.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     nf.ctypes.data_as(C.POINTER(C.c_int32)), o.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     bc.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)))
+        self.h = h
+        self._arrs = None
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pmg_mesh_destroy(self.h)
+            self.h = None
+
+
+def physics_struct(ph) -> Physics:
+    return Physics(ph.mach, ph.reynolds, ph.prandtl, ph.gamma, ph.sutherland, ph.cfl_adv, ph.cfl_visc,
+                   int(ph.family), int(ph.viscosity))
+
+
+class Solver:
+    """mesh + orders + physics + multigrid hierarchy on one GPU."""
+
+    def __init__(self, ctx: Context, mesh: Mesh, orders, phys, mg: MG = MG()):
+        import torch
+        self.ctx, self.mesh, self.phys, self.mg = ctx, mesh, phys, mg
+        self.torch = torch
+        self.device = torch.device("cuda", ctx.device)
+        orders = np.ascontiguousarray(orders, dtype=np.int32)
+        self.orders = orders
+        caps = None if mg.level_caps is None else np.asarray(mg.level_caps, dtype=np.int32)
+        self._caps = caps
+        p = MGParams(0 if caps is None else len(caps),
+                     None if caps is None else caps.ctypes.data_as(C.POINTER(C.c_int32)),
+                     mg.beta_pre, mg.beta_post, mg.beta_coarse, mg.tuning, mg.eta, mg.max_repeats, mg.fmg,
+                     mg.fmg_threshold)
+        ph = physics_struct(phys)
+        h = C.c_void_p()
+        _check(lib().pmg_solver_create(ctx.h, mesh.h, orders.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(ph),
+                                       C.byref(p), C.byref(h)))
+        self.h = h
+        nn = C.c_int64()
+        off = np.zeros(mesh.K + 1, dtype=np.int64)
+        _check(lib().pmg_state_layout(h, C.byref(nn), off.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.n_nodes = int(nn.value)
+        self.offsets = off
+        self.nmax = int(orders.max())
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pmg_solver_destroy(self.h)
+            self.h = None
+
+    # -- helpers --------------------------------------------------------------------------------------
+    def empty(self, n: Optional[int] = None):
+        return self.torch.empty((5, self.n_nodes if n is None else n), dtype=self.torch.float64, device=self.device)
+
+    def tensor(self, a):
+        return self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.device)
+
+    # -- entry points -----------------------------------------------------------------------------------
+    def freestream(self):
+        Q = self.empty()
+        _check(lib().pmg_init_freestream(self.h, _ptr(Q), _stream()))
+        return Q
+
+    def residual(self, Q, S=None, isolated=False, out=None, norm=False):
+        out = self.empty() if out is None else out
+        r = C.c_double()
+        _check(lib().pmg_residual(self.h, int(bool(isolated)), _ptr(Q), _ptr(S), _ptr(out),
+                                  C.byref(r) if norm else None, _stream()))
+        return (out, r.value) if norm else out
+
+    def timestep(self, Q) -> float:
+        dt = C.c_double()
+        _check(lib().pmg_timestep(self.h, _ptr(Q), C.byref(dt), _stream()))
+        return dt.value
+
+    def smooth(self, Q, S=None, sweeps=1):
+        _check(lib().pmg_smooth(self.h, _ptr(Q), _ptr(S), int(sweeps), _stream()))
+        return Q
+
+    def level_info(self, hierarchy: int, level: int = -1):
+        nl = C.c_int32()
+        nn = C.c_int64()
+        if level < 0:
+            _check(lib().pmg_level_info(self.h, hierarchy, -1, C.byref(nl), None, None))
+            return int(nl.value)
+        orders = np.zeros((self.mesh.K, 3), dtype=np.int32)
+        _check(lib().pmg_level_info(self.h, hierarchy, level, C.byref(nl), C.byref(nn),
+                                    orders.ctypes.data_as(C.POINTER(C.c_int32))))
+        return int(nn.value), orders
+
+    def restrict(self, hierarchy: int, level: int, U):
+        nn, _ = self.level_info(hierarchy, level - 1)
+        out = self.empty(nn)
+        _check(lib().pmg_restrict(self.h, hierarchy, level, _ptr(U), _ptr(out), _stream()))
+        return out
+
+    def prolong(self, hierarchy: int, level: int, U):
+        nn, _ = self.level_info(hierarchy, level + 1)
+        out = self.empty(nn)
+        _check(lib().pmg_prolong(self.h, hierarchy, level, _ptr(U), _ptr(out), _stream()))
+        return out
+
+    def vcycle(self, Q, S=None, n_cycles=1, norm=False):
+        r = C.c_double()
+        _check(lib().pmg_vcycle(self.h, _ptr(Q), _ptr(S), int(n_cycles), C.byref(r) if norm else None, _stream()))
+        return r.value if norm else None
+
+    def solve(self, Q, S=None, tol=1e-9, max_cycles=100, raise_not_converged=True):
+        cyc = C.c_int32()
+        r = C.c_double()
+        rc = lib().pmg_solve(self.h, _ptr(Q), _ptr(S), float(tol), int(max_cycles), C.byref(cyc), C.byref(r), _stream())
+        if rc != 0 and (rc != 5 or raise_not_converged):
+            _check(rc)
+        return int(cyc.value), float(r.value)
+
+    def tau_estimate(self, Q, S=None, isolated=True):
+        nt = max(self.nmax - 1, 1)
+        tau = self.torch.empty((self.mesh.K, 3, nt), dtype=self.torch.float64, device=self.device)
+        _check(lib().pmg_tau_estimate(self.h, _ptr(Q), _ptr(S), int(bool(isolated)), _ptr(tau), _stream()))
+        return tau

@@ -1,0 +1,42 @@
+"""CPU checks of the C-ABI library: it loads and exports every entry point include/pmg.h declares.
+(No compute call: there is no GPU here.)"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pmg.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path():
+    names = declared()
+    for n in ("pmg_residual", "pmg_vcycle", "pmg_tau_estimate", "pmg_solve", "pmg_restrict", "pmg_prolong",
+              "pmg_smooth", "pmg_timestep", "pmg_solver_create", "pmg_mesh_create"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1806_11456_amd import pmg
+    if not os.path.exists(pmg.LIB_PATH):
+        from paper_1806_11456_amd import build
+        build.build()
+    lib = ctypes.CDLL(pmg.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(pmg.EXPORTS) == declared()
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1806_11456_amd import pmg
+    monkeypatch.setattr(pmg, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(pmg, "_lib", None)
+    with pytest.raises(RuntimeError):
+        pmg.lib()
