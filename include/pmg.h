@@ -180,6 +180,18 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
 pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, int isolated, double* tau_map_dev,
                             void* stream);
 
+/*
+ * Kernel timing with HIP events (diagnostics).  mask selects kernel kinds (bit k = kind k):
+ * 0 face traces, 1 interface state + Roe flux, 2 BR1 gradient, 3 viscous numerical flux, 4 divergence
+ * and epilogue, 5 CFL step, 6 transfers.  While enabled, every launch of a selected kind is bracketed by
+ * two events on its stream.  pmg_profile_read waits for the recorded events and returns, for one kind,
+ * the summed event-to-event time, the number of launches and the summed compulsory bytes of those launches
+ * (every input array read once, every output written once, at the launched level's sizes) since the last
+ * read of that kind; alg_bytes may be NULL.
+ */
+pmg_status pmg_profile_enable(pmg_solver s, uint32_t mask);
+pmg_status pmg_profile_read(pmg_solver s, int kind, double* total_ms, int64_t* launches, double* alg_bytes);
+
 #ifdef __cplusplus
 }
 #endif

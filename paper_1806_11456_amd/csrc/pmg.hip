@@ -142,7 +142,74 @@ struct Hier {
   int top() const { return (int)lv.size() - 1; }
 };
 
+// Event timing of selected kernel kinds (pmg_profile_enable / pmg_profile_read).
+enum { PK_TRACE = 0, PK_FACE1 = 1, PK_GRAD = 2, PK_FACE2 = 3, PK_DIV = 4, PK_DT = 5, PK_XFER = 6, PK_N = 7 };
+
+struct Prof {
+  uint32_t mask = 0;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  struct Rec {
+    int kind;
+    size_t ev;     // first of the two events
+    double bytes;  // compulsory bytes of the launch
+  };
+  std::vector<Rec> recs;
+  ~Prof() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+  bool on(int kind) const { return (mask >> kind) & 1u; }
+  size_t begin(int kind, hipStream_t st) {
+    if (!((mask >> kind) & 1u)) return SIZE_MAX;
+    while (pool.size() < next + 2) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    size_t i = next;
+    next += 2;
+    HIPCHECK(hipEventRecord(pool[i], st));
+    return i;
+  }
+  void end(int kind, size_t i, double bytes, hipStream_t st) {
+    if (i == SIZE_MAX) return;
+    HIPCHECK(hipEventRecord(pool[i + 1], st));
+    recs.push_back({kind, i, bytes});
+  }
+  void read(int kind, double* ms, int64_t* n, double* bytes) {
+    double tot = 0.0, b = 0.0;
+    int64_t cnt = 0;
+    std::vector<Rec> keep;
+    for (auto& r : recs) {
+      if (r.kind != kind) {
+        keep.push_back(r);
+        continue;
+      }
+      HIPCHECK(hipEventSynchronize(pool[r.ev + 1]));
+      float t = 0.f;
+      HIPCHECK(hipEventElapsedTime(&t, pool[r.ev], pool[r.ev + 1]));
+      tot += t;
+      b += r.bytes;
+      cnt++;
+    }
+    recs.swap(keep);
+    if (recs.empty()) next = 0;
+    *ms = tot;
+    *n = cnt;
+    if (bytes) *bytes = b;
+  }
+};
+
+// Launch bracketed by events when its kind is selected; 'bytes' is the launch's compulsory traffic.
+#define PROF_LAUNCH(s, kind, st, bytes, ...)          \
+  do {                                                \
+    size_t pi_ = (s)->prof->begin((kind), (st));      \
+    __VA_ARGS__;                                      \
+    if (pi_ != SIZE_MAX) (s)->prof->end((kind), pi_, (double)(bytes), (st)); \
+  } while (0)
+
 struct pmg_solver_s {
+  std::unique_ptr<Prof> prof = std::make_unique<Prof>();
   pmg_ctx ctx;
   pmg_mesh mesh;
   Phys phys;
@@ -366,14 +433,34 @@ static DivArgs div_args(int mode) {
 static void op_eval(const pmg_solver_s* s, Level& L, const double* Q, bool isolated, const DivArgs& a,
                     hipStream_t st) {
   const LevelDev& D = L.dev;
-  k_trace<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, 5, L.d_qf);
-  if (isolated) k_face1_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_Phi);
-  else k_face1<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_PhiA);
-  k_grad<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, s->phys, Q, L.d_Ws, L.d_gW);
-  k_trace<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, L.d_gW, 12, L.d_gf);
-  if (isolated) k_face2_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_Phi);
-  else k_face2<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_PhiA, L.d_Phi);
-  k_div<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(D, s->phys, Q, L.d_gW, L.d_Phi, a);
+  const double nn = L.nn, nf = L.nf, nm = L.nm, w = sizeof(double);
+  PROF_LAUNCH(s, PK_TRACE, st, (5 * nn + 5 * nf) * w, k_trace<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, 5, L.d_qf));
+  if (isolated)
+    PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 3 * nf + 4 * nf + 5 * nf) * w,
+                k_face1_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_Phi));
+  else
+    PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nm + 4 * nf + 5 * nf) * w,
+                k_face1<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_PhiA));
+  PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn) * w,
+              k_grad<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, s->phys, Q, L.d_Ws, L.d_gW));
+  PROF_LAUNCH(s, PK_TRACE, st, (12 * nn + 12 * nf) * w, k_trace<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, L.d_gW, 12, L.d_gf));
+  if (isolated)
+    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 2 * 4 * nf) * w,
+                k_face2_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_Phi));
+  else
+    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 4 * nm + 5 * nf + 5 * nf) * w,
+                k_face2<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_PhiA, L.d_Phi));
+  // divergence: Q, grad W, J a, 1/J, Phi in; the epilogue's own arrays
+  double epi = 0.0;
+  switch (a.mode) {
+    case EPI_R: epi = (a.S ? 5 : 0) * nn + 5 * nn; break;
+    case EPI_RK: epi = (a.S ? 5 : 0) * nn + (a.a != 0.0 ? 5 : 0) * nn + 10 * nn; break;
+    case EPI_SRC: epi = 10 * nn + ((a.tau_map && a.Sphys) ? 5 * nn : 0); break;
+    case EPI_TAU: epi = a.Sphys ? 5 * nn : 0; break;
+    default: epi = 5 * nn;
+  }
+  PROF_LAUNCH(s, PK_DIV, st, (27 * nn + 5 * nf + epi) * w,
+              k_div<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(D, s->phys, Q, L.d_gW, L.d_Phi, a));
 }
 
 static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
@@ -399,7 +486,8 @@ static double read_slot(const pmg_solver_s* s, int slot, hipStream_t st) {
 
 static void timestep(const pmg_solver_s* s, Level& L, const double* Q, hipStream_t st) {
   reset_slot(s, SLOT_DT, INFINITY, st);
-  k_dt<<<L.ntiles, PMG_BLOCK, 0, st>>>(L.dev, s->phys, Q, s->d_red + SLOT_DT);
+  PROF_LAUNCH(s, PK_DT, st, 15.0 * L.nn * sizeof(double),
+              k_dt<<<L.ntiles, PMG_BLOCK, 0, st>>>(L.dev, s->phys, Q, s->d_red + SLOT_DT));
 }
 
 static void smooth(const pmg_solver_s* s, Level& L, double* Q, const double* S, double* G, int sweeps,
@@ -432,7 +520,8 @@ static void residual(const pmg_solver_s* s, Level& L, const double* Q, const dou
   op_eval(s, L, Q, isolated, a, st);
 }
 
-static void xfer(const Level& from, const Level& to, const XferTiles& X, bool prolong, const double* U,
+static void xfer(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
+                 const double* U,
                  const double* U0, double* V, bool accumulate, hipStream_t st) {
   XferArgs a;
   a.tiles = prolong ? X.d_prolong : X.d_restrict;
@@ -447,7 +536,9 @@ static void xfer(const Level& from, const Level& to, const XferTiles& X, bool pr
   a.V = V;
   a.accumulate = accumulate ? 1 : 0;
   a.lds_stride = X.lds_stride;
-  k_transfer<<<X.ntiles, PMG_BLOCK, (size_t)10 * X.lds_stride * sizeof(double), st>>>(a);
+  PROF_LAUNCH(s, PK_XFER, st,
+              (5.0 * from.nn * (U0 ? 2 : 1) + 5.0 * to.nn * (accumulate ? 2 : 1)) * sizeof(double),
+              k_transfer<<<X.ntiles, PMG_BLOCK, (size_t)10 * X.lds_stride * sizeof(double), st>>>(a));
 }
 
 static void copy(double* dst, const double* src, size_t n, hipStream_t st) {
@@ -509,7 +600,7 @@ struct CycleCtx {
 
 static void restrict_to(CycleCtx& c, int l, const double* Uf, double* Uc) {
   Hier& H = *c.H;
-  xfer(*H.lv[l], *H.lv[l - 1], *H.xf[l - 1], false, Uf, nullptr, Uc, false, c.st);
+  xfer(c.s, *H.lv[l], *H.lv[l - 1], *H.xf[l - 1], false, Uf, nullptr, Uc, false, c.st);
 }
 
 static void absmax(CycleCtx& c, const double* U, size_t n, int slot) {
@@ -599,11 +690,11 @@ static void vcycle_rec(CycleCtx& c, int l, int top) {
   double rpre = pre_smooth(c, l, top);
   if (l > 0) {
     Level& Lc = *H.lv[l - 1];
-    xfer(L, Lc, *H.xf[l - 1], false, H.Q[l], nullptr, H.Q[l - 1], false, c.st);
-    if (!s->mg.tuning) xfer(L, Lc, *H.xf[l - 1], false, H.R[l], nullptr, H.r[l - 1], false, c.st);
+    xfer(s, L, Lc, *H.xf[l - 1], false, H.Q[l], nullptr, H.Q[l - 1], false, c.st);
+    if (!s->mg.tuning) xfer(s, L, Lc, *H.xf[l - 1], false, H.R[l], nullptr, H.r[l - 1], false, c.st);
     vcycle_rec(c, l - 1, top);
     // Q <- Q + I (Q~c - Q~c_0)   (eqs. FASIterError, FASCorrectSol)
-    xfer(Lc, L, *H.xf[l - 1], true, H.Q[l - 1], H.Q0[l - 1], H.Q[l], true, c.st);
+    xfer(s, Lc, L, *H.xf[l - 1], true, H.Q[l - 1], H.Q0[l - 1], H.Q[l], true, c.st);
     post_smooth(c, l, rpre);
   }
 }
@@ -842,7 +933,7 @@ pmg_status pmg_restrict(pmg_solver s, int hierarchy, int level, const double* Uf
     REQUIRE(s && Uf && Uc, "NULL argument");
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 1 && level < (int)H.lv.size(), "level out of range");
-    xfer(*H.lv[level], *H.lv[level - 1], *H.xf[level - 1], false, Uf, nullptr, Uc, false, (hipStream_t)stream);
+    xfer(s, *H.lv[level], *H.lv[level - 1], *H.xf[level - 1], false, Uf, nullptr, Uc, false, (hipStream_t)stream);
     HIPCHECK(hipGetLastError());
   });
 }
@@ -852,7 +943,7 @@ pmg_status pmg_prolong(pmg_solver s, int hierarchy, int level, const double* Uc,
     REQUIRE(s && Uf && Uc, "NULL argument");
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 0 && level + 1 < (int)H.lv.size(), "level out of range");
-    xfer(*H.lv[level], *H.lv[level + 1], *H.xf[level], true, Uc, nullptr, Uf, false, (hipStream_t)stream);
+    xfer(s, *H.lv[level], *H.lv[level + 1], *H.xf[level], true, Uc, nullptr, Uf, false, (hipStream_t)stream);
     HIPCHECK(hipGetLastError());
   });
 }
@@ -897,7 +988,7 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
           vcycle_rec(c, l, l);
           cycles++;
         }
-        xfer(L, *H.lv[l + 1], *H.xf[l], true, H.Q[l], nullptr, H.Q[l + 1], false, st);
+        xfer(s, L, *H.lv[l + 1], *H.xf[l], true, H.Q[l], nullptr, H.Q[l + 1], false, st);
       }
     }
     copy(H.S[top], H.Sp[top], 5 * (size_t)H.lv[top]->nn, st);
@@ -933,6 +1024,22 @@ pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, in
       run_vcycles(s, H, Q_dev, S_dev, 1, &tau, st);
     }
     HIPCHECK(hipGetLastError());
+  });
+}
+
+pmg_status pmg_profile_enable(pmg_solver s, uint32_t mask) {
+  return guard([&] {
+    REQUIRE(s, "NULL solver");
+    REQUIRE((mask >> PK_N) == 0, "unknown kernel kind in mask");
+    s->prof->mask = mask;
+  });
+}
+
+pmg_status pmg_profile_read(pmg_solver s, int kind, double* total_ms, int64_t* launches, double* alg_bytes) {
+  return guard([&] {
+    REQUIRE(s && total_ms && launches, "NULL argument");
+    REQUIRE(kind >= 0 && kind < PK_N, "unknown kernel kind");
+    s->prof->read(kind, total_ms, launches, alg_bytes);
   });
 }
 

@@ -23,7 +23,10 @@ STATUS = {0: "PMG_OK", 1: "PMG_ERR_INVALID_ARG", 2: "PMG_ERR_OOM", 3: "PMG_ERR_H
 EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_create", "pmg_mesh_destroy",
            "pmg_solver_create", "pmg_solver_destroy", "pmg_state_layout", "pmg_init_freestream", "pmg_residual",
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
-           "pmg_solve", "pmg_tau_estimate"]
+           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read"]
+
+# kernel kinds of pmg_profile_enable / pmg_profile_read
+KINDS = {"trace": 0, "face1": 1, "grad": 2, "face2": 3, "div": 4, "dt": 5, "transfer": 6}
 
 
 class PmgError(RuntimeError):
@@ -89,6 +92,8 @@ def lib():
     L.pmg_vcycle.argtypes = [P, V, V, C.c_int, D, V]
     L.pmg_solve.argtypes = [P, V, V, C.c_double, C.c_int, I32, D, V]
     L.pmg_tau_estimate.argtypes = [P, V, V, C.c_int, V, V]
+    L.pmg_profile_enable.argtypes = [P, C.c_uint32]
+    L.pmg_profile_read.argtypes = [P, C.c_int, D, I64, D]
     for name in EXPORTS:
         if name not in ("pmg_last_error", "pmg_ctx_destroy", "pmg_mesh_destroy", "pmg_solver_destroy"):
             getattr(L, name).restype = C.c_int
@@ -251,6 +256,21 @@ class Solver:
         if rc != 0 and (rc != 5 or raise_not_converged):
             _check(rc)
         return int(cyc.value), float(r.value)
+
+    def profile(self, kinds):
+        """Bracket every launch of the given kernel kinds with HIP events (empty = off)."""
+        mask = 0
+        for k in kinds:
+            mask |= 1 << KINDS[k]
+        _check(lib().pmg_profile_enable(self.h, mask))
+
+    def profile_read(self, kind: str):
+        """(summed milliseconds, launches, summed compulsory bytes) of one kind since its last read."""
+        ms = C.c_double()
+        n = C.c_int64()
+        b = C.c_double()
+        _check(lib().pmg_profile_read(self.h, KINDS[kind], C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, int(n.value), b.value
 
     def tau_estimate(self, Q, S=None, isolated=True):
         nt = max(self.nmax - 1, 1)
