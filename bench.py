@@ -54,6 +54,8 @@ def main() -> int:
     ap.add_argument("--residual-loops", type=int, default=200)
     ap.add_argument("--cpu-evals", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -67,6 +69,13 @@ def main() -> int:
 
     from paper_1806_11456_amd import inputs as I
     from paper_1806_11456_amd import pmg
+
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     wl = I.config_plate()
     ctx = pmg.Context(0)

@@ -120,6 +120,7 @@ struct Level {
   double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;
   double *d_qf, *d_Ws, *d_gW, *d_gf, *d_PhiA, *d_Phi;
   LevelDev dev;
+  size_t lds_trace() const { return (size_t)5 * max_tile * sizeof(double); }
   size_t lds_grad() const { return (size_t)13 * max_tile * sizeof(double); }
   size_t lds_div() const { return (size_t)15 * max_tile * sizeof(double); }
 };
@@ -163,7 +164,8 @@ struct Prof {
     if (!((mask >> kind) & 1u)) return SIZE_MAX;
     while (pool.size() < next + 2) {
       hipEvent_t e;
-      HIPCHECK(hipEventCreate(&e));
+      // device-scope release only: the timer does not need a system-wide fence around each kernel
+      HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       pool.push_back(e);
     }
     size_t i = next;
@@ -434,16 +436,16 @@ static void op_eval(const pmg_solver_s* s, Level& L, const double* Q, bool isola
                     hipStream_t st) {
   const LevelDev& D = L.dev;
   const double nn = L.nn, nf = L.nf, nm = L.nm, w = sizeof(double);
-  PROF_LAUNCH(s, PK_TRACE, st, (5 * nn + 5 * nf) * w, k_trace<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, 5, L.d_qf));
+  PROF_LAUNCH(s, PK_TRACE, st, (5 * nn + 5 * nf) * w,
+              k_trace<<<L.ntiles, PMG_BLOCK, L.lds_trace(), st>>>(D, Q, L.d_qf));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 3 * nf + 4 * nf + 5 * nf) * w,
                 k_face1_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_Phi));
   else
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nm + 4 * nf + 5 * nf) * w,
                 k_face1<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_PhiA));
-  PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn) * w,
-              k_grad<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, s->phys, Q, L.d_Ws, L.d_gW));
-  PROF_LAUNCH(s, PK_TRACE, st, (12 * nn + 12 * nf) * w, k_trace<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, L.d_gW, 12, L.d_gf));
+  PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn + 12 * nf) * w,
+              k_grad<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, s->phys, Q, L.d_Ws, L.d_gW, L.d_gf));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 2 * 4 * nf) * w,
                 k_face2_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_Phi));
