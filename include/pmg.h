@@ -181,6 +181,39 @@ pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, in
                             void* stream);
 
 /*
+ * Batches of independent steady problems (many solves advanced together by the same V-cycle).  The n
+ * problems become one solver over the union of their elements (no faces between problems): every kernel
+ * launch covers all problems, elements are bucketed per (problem, order triple), and the explicit step and
+ * the residual norms are reduced per problem, so each problem's arithmetic is the same as in its own solve.
+ * Requirements: one node family and the same maximum order for all problems (their level sequences then
+ * coincide), fixed sweep counts (no residual-based tuning).  Mapping orders may differ (lower ones are
+ * raised exactly).  The batch state is the concatenation of the problems' states in problem order
+ * ([5][total nodes]); pmg_batch_layout gives the n+1 node offsets.  All single-problem entry points
+ * accept a batch handle and act on every problem at once.
+ */
+pmg_status pmg_batch_create(pmg_ctx ctx, int n, const pmg_mesh* meshes, const int32_t* const* orders,
+                            const pmg_physics* phys /* n entries */, const pmg_mg_params* mg, pmg_solver* out);
+pmg_status pmg_batch_layout(pmg_solver s, int* n_problems, int64_t* problem_node_offset /* n+1, nullable */);
+/* res_inf_host: host, n entries, max |S - A(Q)| of each problem (waits for the stream). */
+pmg_status pmg_batch_norms(pmg_solver s, const double* Q_dev, const double* S_dev, double* res_inf_host,
+                           void* stream);
+/* V-cycles until every problem is below tol; a converged problem is frozen (its RK updates take a zero
+ * step, so its state no longer changes) while the others continue.  cycles_out / res_inf_out: n entries. */
+pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, double tol, int max_cycles,
+                           int32_t* cycles_out, double* res_inf_out, void* stream);
+
+/*
+ * Graph mode: with enable = 1, pmg_vcycle, pmg_batch_solve (cycles) and pmg_tau_estimate replay a HIP graph
+ * captured once per (state, source, tau map) pointers on the first call, instead of launching every kernel
+ * from the host (only for fixed sweep counts).  Results are identical to the eager launches.
+ */
+pmg_status pmg_set_graph(pmg_solver s, int enable);
+/* Tile autotuner: times the operator on every built level for element tiles of about 64, 128, 256 and 512
+ * nodes and keeps the fastest (cached per context by the level's order-bucket histogram). */
+pmg_status pmg_autotune(pmg_solver s, void* stream);
+pmg_status pmg_level_tiles(pmg_solver s, int hierarchy, int level, int32_t* tile_target);
+
+/*
  * Kernel timing with HIP events (diagnostics).  mask selects kernel kinds (bit k = kind k):
  * 0 face traces, 1 interface state + Roe flux, 2 BR1 gradient, 3 viscous numerical flux, 4 divergence
  * and epilogue, 5 CFL step, 6 transfers.  While enabled, every launch of a selected kind is bracketed by

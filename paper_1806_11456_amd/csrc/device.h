@@ -51,6 +51,11 @@ struct FaceRec {
 
 struct LevelDev {
   int K, nn, nf, nm, fam;
+  const Phys* __restrict__ ptab;   // physics of each problem of the batch
+  const int* __restrict__ eprob;   // problem of each element
+  const int* __restrict__ node_elem;  // element of each node
+  const double* __restrict__ dt;   // per-problem explicit step (device scalars, read by the RK epilogue)
+  const int* __restrict__ active;  // per-problem: 0 = frozen (its RK updates use a zero step)
   const int* __restrict__ ord;   // K*3 orders
   const int* __restrict__ off;   // K+1 node offsets
   const int* __restrict__ fo;    // K*6 face-node offsets

@@ -10,6 +10,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pmg.h"
@@ -63,7 +64,7 @@ pmg_status guard(F&& f) {
 
 inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 
-// device allocation owned by a level / solver
+// device allocations owned by a level / solver
 struct DevArena {
   std::vector<void*> ptrs;
   template <class T>
@@ -96,6 +97,7 @@ struct pmg_ctx_s {
   int device = 0;
   DevArena arena;
   double* T[2] = {nullptr, nullptr};  // transfer tables per family
+  std::map<std::string, int> tile_cache;  // autotuned tile targets keyed by level structure
 };
 
 struct pmg_mesh_s {
@@ -112,8 +114,9 @@ struct pmg_mesh_s {
 struct Level {
   int K = 0, nn = 0, nf = 0, nm = 0, fam = 0;
   std::vector<int> ord, off, fo;
-  int ntiles = 0, nftiles = 0, max_tile = 0;
+  int ntiles = 0, nftiles = 0, max_tile = 0, tile_target = 256;
   DevArena arena;
+  DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile;
   int4* d_tiles;
   FaceRec* d_faces;
@@ -159,7 +162,6 @@ struct Prof {
   ~Prof() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
-  bool on(int kind) const { return (mask >> kind) & 1u; }
   size_t begin(int kind, hipStream_t st) {
     if (!((mask >> kind) & 1u)) return SIZE_MAX;
     while (pool.size() < next + 2) {
@@ -174,7 +176,6 @@ struct Prof {
     return i;
   }
   void end(int kind, size_t i, double bytes, hipStream_t st) {
-    if (i == SIZE_MAX) return;
     HIPCHECK(hipEventRecord(pool[i + 1], st));
     recs.push_back({kind, i, bytes});
   }
@@ -203,42 +204,104 @@ struct Prof {
 };
 
 // Launch bracketed by events when its kind is selected; 'bytes' is the launch's compulsory traffic.
-#define PROF_LAUNCH(s, kind, st, bytes, ...)          \
-  do {                                                \
-    size_t pi_ = (s)->prof->begin((kind), (st));      \
-    __VA_ARGS__;                                      \
-    if (pi_ != SIZE_MAX) (s)->prof->end((kind), pi_, (double)(bytes), (st)); \
+#define PROF_LAUNCH(s, kind, st, bytes, ...)                                     \
+  do {                                                                           \
+    size_t pi_ = (s)->prof->begin((kind), (st));                                 \
+    __VA_ARGS__;                                                                 \
+    if (pi_ != SIZE_MAX) (s)->prof->end((kind), pi_, (double)(bytes), (st));     \
   } while (0)
+
+// Captured V-cycles / truncation-error cycles, replayed with hipGraphLaunch.
+struct GraphKey {
+  int kind;  // 0 isotropic V-cycle, 1 anisotropic 3V tau cycle
+  const void *Q, *S, *tau;
+  int isolated;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(kind, Q, S, tau, isolated) < std::tie(o.kind, o.Q, o.S, o.tau, o.isolated);
+  }
+};
 
 struct pmg_solver_s {
   std::unique_ptr<Prof> prof = std::make_unique<Prof>();
-  pmg_ctx ctx;
-  pmg_mesh mesh;
-  Phys phys;
+  pmg_ctx ctx = nullptr;
+  const pmg_mesh_s* mesh = nullptr;          // the (union) mesh
+  std::unique_ptr<pmg_mesh_s> own_mesh;      // union mesh of a batch
+  int nprob = 1;
+  int family = 0;
+  std::vector<Phys> phys;                    // per problem
+  std::vector<int> eprob;                    // problem of each element
+  std::vector<int> prob_elem;                // first element of each problem (nprob+1)
   pmg_mg_params mg;
   std::vector<int> orders;
   std::shared_ptr<Level> top;
   Hier iso;
   std::unique_ptr<Hier> aniso[3];
   DevArena arena;
-  unsigned long long* d_red = nullptr;  // reduction slots
-  double* d_zero = nullptr;             // [5][nn] zeros (absent source)
-  double* d_R = nullptr;                // [5][nn] top-level scratch residual
-  double* d_G = nullptr;                // [5][nn] top-level RK register
+  Phys* d_ptab = nullptr;
+  int* d_eprob = nullptr;
+  int* d_active = nullptr;                   // per problem: 0 frozen
+  unsigned long long* d_red = nullptr;       // reduction slots [NSLOTS][nprob]
+  double* d_zero = nullptr;                  // [5][nn] zeros (absent source)
+  double* d_R = nullptr;                     // [5][nn] top-level scratch residual
+  double* d_G = nullptr;                     // [5][nn] top-level RK register
   int nmax = 1;
+  int use_graph = 0;
+  hipStream_t cap_stream = nullptr;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  ~pmg_solver_s() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
+
+enum { SLOT_DT = 0, SLOT_NORM = 1, SLOT_NORM2 = 2, NSLOTS = 3 };
+
+static unsigned long long* slot_ptr(const pmg_solver_s* s, int slot) { return s->d_red + (size_t)slot * s->nprob; }
 
 // ------------------------------------------------------------------------------------------------
 // Level construction (Sec. 2 geometry; tiles and faces)
 // ------------------------------------------------------------------------------------------------
-static const int TILE_TARGET = 256;
+// Element tiles: elements bucketed by (problem, order triple), packed to about 'target' nodes (one element
+// when larger), so every tile has one order triple and one problem.
+static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
+  std::map<std::pair<int, int>, std::vector<int>> buckets;
+  for (int e = 0; e < L.K; e++)
+    buckets[{s->eprob[e], pack3(L.ord[3 * e] + 1, L.ord[3 * e + 1] + 1, L.ord[3 * e + 2] + 1)}].push_back(e);
+  std::vector<int> elist;
+  std::vector<int4> tiles;
+  int max_tile = 1;
+  for (auto& kv : buckets) {
+    int key = kv.first.second;
+    int n1 = key & 255, n2 = (key >> 8) & 255, n3 = key >> 16;
+    int npe = n1 * n2 * n3;
+    int per = std::max(1, std::min(PMG_MAX_TILE_ELEMS, target / npe));
+    while (per > 1 && per * npe > PMG_TILE_MAX) per--;
+    const auto& es = kv.second;
+    for (size_t i = 0; i < es.size(); i += per) {
+      int cnt = (int)std::min<size_t>(per, es.size() - i);
+      tiles.push_back(make_int4((int)elist.size(), cnt, key, cnt * npe));
+      max_tile = std::max(max_tile, cnt * npe);
+      for (int c = 0; c < cnt; c++) elist.push_back(es[i + c]);
+    }
+  }
+  REQUIRE(max_tile <= PMG_TILE_MAX, "element tile too large");
+  L.tile_arena.~DevArena();
+  new (&L.tile_arena) DevArena();
+  L.d_elist = L.tile_arena.upload(elist);
+  L.d_tiles = L.tile_arena.upload(tiles);
+  L.ntiles = (int)tiles.size();
+  L.max_tile = max_tile;
+  L.tile_target = target;
+  L.dev.tiles = L.d_tiles;
+  L.dev.elist = L.d_elist;
+}
 
 static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int>& ord) {
-  pmg_mesh m = s->mesh;
+  const pmg_mesh_s* m = s->mesh;
   auto L = std::make_shared<Level>();
   const int K = (int)m->K;
   L->K = K;
-  L->fam = s->phys.family;
+  L->fam = s->family;
   L->ord = ord;
   L->off.assign(K + 1, 0);
   L->fo.assign(6 * K, 0);
@@ -253,35 +316,14 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
       nf += fs[f / 2];
     }
   }
-  REQUIRE(5 * nn < (1ll << 31) && 12 * nf < (1ll << 31), "mesh too large for 32-bit node indexing");
+  REQUIRE(12 * nn < (1ll << 31) && 12 * nf < (1ll << 31), "mesh too large for 32-bit node indexing");
   L->off[K] = (int)nn;
   L->nn = (int)nn;
   L->nf = (int)nf;
 
-  // element tiles: elements bucketed by order triple
-  std::map<int, std::vector<int>> buckets;
-  for (int e = 0; e < K; e++) buckets[pack3(ord[3 * e] + 1, ord[3 * e + 1] + 1, ord[3 * e + 2] + 1)].push_back(e);
-  std::vector<int> elist;
-  std::vector<int4> tiles;
-  int max_tile = 1;
-  for (auto& kv : buckets) {
-    int n1 = kv.first & 255, n2 = (kv.first >> 8) & 255, n3 = kv.first >> 16;
-    int npe = n1 * n2 * n3;
-    int per = std::max(1, std::min(PMG_MAX_TILE_ELEMS, TILE_TARGET / npe));
-    const auto& es = kv.second;
-    for (size_t i = 0; i < es.size(); i += per) {
-      int cnt = (int)std::min<size_t>(per, es.size() - i);
-      tiles.push_back(make_int4((int)elist.size(), cnt, kv.first, cnt * npe));
-      max_tile = std::max(max_tile, cnt * npe);
-      for (int c = 0; c < cnt; c++) elist.push_back(es[i + c]);
-    }
-  }
-  REQUIRE(max_tile <= PMG_TILE_MAX, "element tile too large");
-  L->ntiles = (int)tiles.size();
-  L->max_tile = max_tile;
-
   // faces: one record per interface (master side) and per boundary face
   std::vector<FaceRec> faces;
+  std::vector<int> fprob;
   for (int e = 0; e < K; e++)
     for (int f = 0; f < 6; f++) {
       int64_t g = m->nbr[6 * e + f];
@@ -313,17 +355,23 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
       }
       faces.push_back(F);
     }
-  // order faces by mortar size (uniform lanes per tile), then pack into tiles of <= PMG_FACE_TILE lanes
-  std::stable_sort(faces.begin(), faces.end(),
-                   [](const FaceRec& a, const FaceRec& b) { return a.ms * a.mt > b.ms * b.mt; });
+  // faces ordered by (problem, mortar size) and packed into tiles of <= PMG_FACE_TILE lanes that never
+  // split a face nor mix problems
+  std::stable_sort(faces.begin(), faces.end(), [&](const FaceRec& a, const FaceRec& b) {
+    int pa = s->eprob[a.eM], pb = s->eprob[b.eM];
+    if (pa != pb) return pa < pb;
+    return a.ms * a.mt > b.ms * b.mt;
+  });
   std::vector<int> ftile{0}, mface;
-  int cur = 0;
+  int cur = 0, cur_prob = faces.empty() ? 0 : s->eprob[faces[0].eM];
   for (size_t i = 0; i < faces.size(); i++) {
     int nmf = faces[i].ms * faces[i].mt;
-    if (cur + nmf > PMG_FACE_TILE) {
+    int p = s->eprob[faces[i].eM];
+    if (cur > 0 && (cur + nmf > PMG_FACE_TILE || p != cur_prob)) {
       ftile.push_back((int)mface.size());
       cur = 0;
     }
+    cur_prob = p;
     faces[i].mbase = (int)mface.size();
     for (int k = 0; k < nmf; k++) mface.push_back((int)i);
     cur += nmf;
@@ -341,8 +389,6 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_off = A.upload(L->off);
   L->d_fo = A.upload(L->fo);
   L->d_node_elem = A.upload(node_elem);
-  L->d_elist = A.upload(elist);
-  L->d_tiles = A.upload(tiles);
   L->d_faces = A.upload(faces);
   L->d_mface = A.upload(mface);
   L->d_ftile = A.upload(ftile);
@@ -359,12 +405,16 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_Phi = A.alloc<double>(5 * nf);
 
   LevelDev& D = L->dev;
+  memset(&D, 0, sizeof(D));
   D.K = K; D.nn = (int)nn; D.nf = (int)nf; D.nm = L->nm; D.fam = L->fam;
+  D.ptab = s->d_ptab; D.eprob = s->d_eprob; D.node_elem = L->d_node_elem;
+  D.dt = (const double*)slot_ptr(s, SLOT_DT);
+  D.active = s->d_active;
   D.ord = L->d_ord; D.off = L->d_off; D.fo = L->d_fo;
   D.Ja = L->d_Ja; D.invJ = L->d_invJ; D.J = L->d_J; D.Nout = L->d_Nout;
-  D.tiles = L->d_tiles; D.elist = L->d_elist;
   D.faces = L->d_faces; D.mface = L->d_mface; D.ftile = L->d_ftile; D.mgeo = L->d_mgeo;
   D.T = s->ctx->T[L->fam];
+  build_tiles(s, *L, 256);
 
   // geometry on the device
   DevArena tmp;
@@ -386,23 +436,23 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   return L;
 }
 
-static std::unique_ptr<XferTiles> build_xfer(const Level& fine, const Level& coarse) {
+static std::unique_ptr<XferTiles> build_xfer(const pmg_solver_s* s, const Level& fine, const Level& coarse) {
   auto X = std::make_unique<XferTiles>();
-  std::map<std::pair<int, int>, std::vector<int>> buckets;
+  std::map<std::tuple<int, int, int>, std::vector<int>> buckets;
   for (int e = 0; e < fine.K; e++) {
     int a = pack3(fine.ord[3 * e] + 1, fine.ord[3 * e + 1] + 1, fine.ord[3 * e + 2] + 1);
     int b = pack3(coarse.ord[3 * e] + 1, coarse.ord[3 * e + 1] + 1, coarse.ord[3 * e + 2] + 1);
-    buckets[{a, b}].push_back(e);
+    buckets[{s->eprob[e], a, b}].push_back(e);
   }
   std::vector<int> elist;
   std::vector<int4> tr, tp;
   int stride = 1;
   for (auto& kv : buckets) {
-    int a = kv.first.first, b = kv.first.second;
+    int a = std::get<1>(kv.first), b = std::get<2>(kv.first);
     int na = (a & 255) * ((a >> 8) & 255) * (a >> 16);
     int nb = (b & 255) * ((b >> 8) & 255) * (b >> 16);
     int big = std::max(na, nb);
-    int per = std::max(1, TILE_TARGET / big);
+    int per = std::max(1, 256 / big);
     const auto& es = kv.second;
     for (size_t i = 0; i < es.size(); i += per) {
       int cnt = (int)std::min<size_t>(per, es.size() - i);
@@ -430,8 +480,8 @@ static DivArgs div_args(int mode) {
   return a;
 }
 
-// A(Q) through the five stages: q traces, interface state, gradient, gradient traces, numerical flux,
-// divergence (the epilogue in 'a' decides what is written).
+// A(Q) through the stages: q traces, interface state + Roe flux, gradient (+ gradient traces), viscous
+// numerical flux, divergence (the epilogue in 'a' decides what is written).
 static void op_eval(const pmg_solver_s* s, Level& L, const double* Q, bool isolated, const DivArgs& a,
                     hipStream_t st) {
   const LevelDev& D = L.dev;
@@ -440,18 +490,18 @@ static void op_eval(const pmg_solver_s* s, Level& L, const double* Q, bool isola
               k_trace<<<L.ntiles, PMG_BLOCK, L.lds_trace(), st>>>(D, Q, L.d_qf));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 3 * nf + 4 * nf + 5 * nf) * w,
-                k_face1_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_Phi));
+                k_face1_iso<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, L.d_qf, L.d_Ws, L.d_Phi));
   else
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nm + 4 * nf + 5 * nf) * w,
-                k_face1<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_Ws, L.d_PhiA));
+                k_face1<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, L.d_qf, L.d_Ws, L.d_PhiA));
   PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn + 12 * nf) * w,
-              k_grad<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, s->phys, Q, L.d_Ws, L.d_gW, L.d_gf));
+              k_grad<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, Q, L.d_Ws, L.d_gW, L.d_gf));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 2 * 4 * nf) * w,
-                k_face2_iso<<<cdiv(L.nf, 256), 256, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_Phi));
+                k_face2_iso<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, L.d_qf, L.d_gf, L.d_Phi));
   else
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 4 * nm + 5 * nf + 5 * nf) * w,
-                k_face2<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, s->phys, L.d_qf, L.d_gf, L.d_PhiA, L.d_Phi));
+                k_face2<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, L.d_qf, L.d_gf, L.d_PhiA, L.d_Phi));
   // divergence: Q, grad W, J a, 1/J, Phi in; the epilogue's own arrays
   double epi = 0.0;
   switch (a.mode) {
@@ -462,34 +512,40 @@ static void op_eval(const pmg_solver_s* s, Level& L, const double* Q, bool isola
     default: epi = 5 * nn;
   }
   PROF_LAUNCH(s, PK_DIV, st, (27 * nn + 5 * nf + epi) * w,
-              k_div<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(D, s->phys, Q, L.d_gW, L.d_Phi, a));
+              k_div<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(D, Q, L.d_gW, L.d_Phi, a));
 }
 
 static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 static const double RK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
-enum { SLOT_DT = 0, SLOT_NORM = 1, SLOT_NORM2 = 2, NSLOTS = 4 };
-
 static void reset_slot(const pmg_solver_s* s, int slot, double v, hipStream_t st) {
   unsigned long long bits;
   memcpy(&bits, &v, sizeof(bits));
-  k_fill_u64<<<1, 64, 0, st>>>(s->d_red + slot, 1, bits);
+  k_fill_u64<<<cdiv(s->nprob, 64), 64, 0, st>>>(slot_ptr(s, slot), s->nprob, bits);
 }
 
-static double read_slot(const pmg_solver_s* s, int slot, hipStream_t st) {
-  unsigned long long bits;
-  HIPCHECK(hipMemcpyAsync(&bits, s->d_red + slot, sizeof(bits), hipMemcpyDeviceToHost, st));
+// per-problem values of a slot (waits for the stream)
+static std::vector<double> read_slots(const pmg_solver_s* s, int slot, hipStream_t st) {
+  std::vector<unsigned long long> bits(s->nprob);
+  HIPCHECK(hipMemcpyAsync(bits.data(), slot_ptr(s, slot), bits.size() * sizeof(bits[0]), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   HIPCHECK(hipGetLastError());
-  double v;
-  memcpy(&v, &bits, sizeof(v));
+  std::vector<double> v(s->nprob);
+  memcpy(v.data(), bits.data(), v.size() * sizeof(double));
   return v;
+}
+
+// max over problems (NaN wins)
+static double read_slot(const pmg_solver_s* s, int slot, hipStream_t st) {
+  double m = 0.0;
+  for (double x : read_slots(s, slot, st)) m = (x > m || x != x) ? x : m;
+  return m;
 }
 
 static void timestep(const pmg_solver_s* s, Level& L, const double* Q, hipStream_t st) {
   reset_slot(s, SLOT_DT, INFINITY, st);
   PROF_LAUNCH(s, PK_DT, st, 15.0 * L.nn * sizeof(double),
-              k_dt<<<L.ntiles, PMG_BLOCK, 0, st>>>(L.dev, s->phys, Q, s->d_red + SLOT_DT));
+              k_dt<<<L.ntiles, PMG_BLOCK, 0, st>>>(L.dev, Q, slot_ptr(s, SLOT_DT)));
 }
 
 static void smooth(const pmg_solver_s* s, Level& L, double* Q, const double* S, double* G, int sweeps,
@@ -501,7 +557,6 @@ static void smooth(const pmg_solver_s* s, Level& L, double* Q, const double* S, 
       a.S = S;
       a.Qrk = Q;
       a.G = G;
-      a.dt = (const double*)(s->d_red + SLOT_DT);
       a.a = RK_A[k];
       a.b = RK_B[k];
       op_eval(s, L, Q, false, a, st);
@@ -509,7 +564,7 @@ static void smooth(const pmg_solver_s* s, Level& L, double* Q, const double* S, 
   }
 }
 
-// out = S - A(Q); optional max-norm into a slot
+// out = S - A(Q); optional per-problem max-norm into a slot
 static void residual(const pmg_solver_s* s, Level& L, const double* Q, const double* S, double* out, bool isolated,
                      int norm_slot, hipStream_t st) {
   DivArgs a = div_args(EPI_R);
@@ -517,14 +572,13 @@ static void residual(const pmg_solver_s* s, Level& L, const double* Q, const dou
   a.out = out;
   if (norm_slot >= 0) {
     reset_slot(s, norm_slot, 0.0, st);
-    a.norm = s->d_red + norm_slot;
+    a.norm = slot_ptr(s, norm_slot);
   }
   op_eval(s, L, Q, isolated, a, st);
 }
 
 static void xfer(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
-                 const double* U,
-                 const double* U0, double* V, bool accumulate, hipStream_t st) {
+                 const double* U, const double* U0, double* V, bool accumulate, hipStream_t st) {
   XferArgs a;
   a.tiles = prolong ? X.d_prolong : X.d_restrict;
   a.elist = X.d_elist;
@@ -545,6 +599,57 @@ static void xfer(const pmg_solver_s* s, const Level& from, const Level& to, cons
 
 static void copy(double* dst, const double* src, size_t n, hipStream_t st) {
   k_copy<<<cdiv(n, 256), 256, 0, st>>>(dst, src, n);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Tile autotuner: per level, the element-tile size with the fastest operator evaluation
+// ------------------------------------------------------------------------------------------------
+static std::string level_key(const pmg_solver_s* s, const Level& L) {
+  // structure = histogram of (order triple) buckets; the tile choice depends only on it
+  std::map<int, int> h;
+  for (int e = 0; e < L.K; e++) h[pack3(L.ord[3 * e], L.ord[3 * e + 1], L.ord[3 * e + 2])]++;
+  std::string k = std::to_string(L.fam) + ":" + std::to_string(s->nprob);
+  for (auto& kv : h) k += "," + std::to_string(kv.first) + "x" + std::to_string(kv.second);
+  return k;
+}
+
+static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
+  std::string key = level_key(s, L);
+  auto it = s->ctx->tile_cache.find(key);
+  if (it != s->ctx->tile_cache.end()) {
+    if (it->second != L.tile_target) build_tiles(s, L, it->second);
+    return;
+  }
+  DevArena tmp;
+  double* Q = tmp.alloc<double>(5 * (size_t)L.nn);
+  double* R = tmp.alloc<double>(5 * (size_t)L.nn);
+  k_freestream<<<cdiv(L.nn, 256), 256, 0, st>>>(L.dev, Q);
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  uint32_t mask = s->prof->mask;
+  s->prof->mask = 0;
+  int best = L.tile_target;
+  float best_t = 1e30f;
+  for (int target : {64, 128, 256, 512}) {
+    build_tiles(s, L, target);
+    residual(s, L, Q, nullptr, R, false, -1, st);  // warm
+    HIPCHECK(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; r++) residual(s, L, Q, nullptr, R, false, -1, st);
+    HIPCHECK(hipEventRecord(e1, st));
+    HIPCHECK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+    if (t < best_t) {
+      best_t = t;
+      best = target;
+    }
+  }
+  s->prof->mask = mask;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best != L.tile_target) build_tiles(s, L, best);
+  s->ctx->tile_cache[key] = best;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -584,7 +689,7 @@ static void build_hier(pmg_solver_s* s, Hier& H, int dir, const std::vector<int>
     H.R[l] = H.arena.alloc<double>(n);
   }
   H.xf.clear();
-  for (int l = 0; l + 1 < nlev; l++) H.xf.push_back(build_xfer(*H.lv[l + 1], *H.lv[l]));
+  for (int l = 0; l + 1 < nlev; l++) H.xf.push_back(build_xfer(s, *H.lv[l + 1], *H.lv[l]));
 }
 
 struct TauRec {
@@ -607,7 +712,7 @@ static void restrict_to(CycleCtx& c, int l, const double* Uf, double* Uc) {
 
 static void absmax(CycleCtx& c, const double* U, size_t n, int slot) {
   reset_slot(c.s, slot, 0.0, c.st);
-  k_absmax<<<std::min(cdiv(n, 256), 2048), 256, 0, c.st>>>(U, n, c.s->d_red + slot);
+  k_absmax<<<std::min(cdiv(n, 256), 2048), 256, 0, c.st>>>(U, n, slot_ptr(c.s, slot));
 }
 
 // pre-smoothing; leaves R[l] = S - A(Q) and returns ||R||_inf when tuning (else 0)
@@ -724,13 +829,204 @@ static void run_vcycles(pmg_solver_s* s, Hier& H, double* Q, const double* S, in
 static Hier& aniso_hier(pmg_solver_s* s, int d) {
   if (!s->aniso[d]) {
     int pmax = 1;
-    for (size_t e = 0; e < s->mesh->K; e++) pmax = std::max(pmax, s->orders[3 * e + d]);
+    for (int64_t e = 0; e < s->mesh->K; e++) pmax = std::max(pmax, s->orders[3 * e + d]);
     std::vector<int> caps;
     for (int c = pmax; c >= 1; c--) caps.push_back(c);
     s->aniso[d] = std::make_unique<Hier>();
     build_hier(s, *s->aniso[d], d, caps);
   }
   return *s->aniso[d];
+}
+
+static void tau_cycles(pmg_solver_s* s, double* Q, const double* S, const TauRec& tau, hipStream_t st) {
+  size_t n = (size_t)s->mesh->K * 3 * tau.nt;
+  k_fill<<<cdiv(n, 256), 256, 0, st>>>(tau.map, n, NAN);
+  for (int d = 0; d < 3; d++) {
+    Hier& H = aniso_hier(s, d);
+    if (H.lv.size() < 2) continue;
+    run_vcycles(s, H, Q, S, 1, &tau, st);
+  }
+}
+
+// Replays a captured graph of 'body' (a fixed launch sequence without host synchronisation) on 'st'.
+template <class F>
+static void run_graph(pmg_solver_s* s, const GraphKey& key, int repeats, hipStream_t st, F&& body) {
+  auto it = s->graphs.find(key);
+  if (it == s->graphs.end()) {
+    if (!s->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    uint32_t mask = s->prof->mask;
+    s->prof->mask = 0;  // no timing events inside a graph
+    HIPCHECK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      body(s->cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(s->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      s->prof->mask = mask;
+      throw;
+    }
+    HIPCHECK(hipStreamEndCapture(s->cap_stream, &g));
+    s->prof->mask = mask;
+    hipGraphExec_t ex = nullptr;
+    HIPCHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    it = s->graphs.emplace(key, ex).first;
+  }
+  for (int r = 0; r < repeats; r++) HIPCHECK(hipGraphLaunch(it->second, st));
+}
+
+// ------------------------------------------------------------------------------------------------
+// Solver construction (one problem or a batch)
+// ------------------------------------------------------------------------------------------------
+static void set_phys(Phys& P, const pmg_physics* ph) {
+  P.gamma = ph->gamma;
+  P.gm1 = ph->gamma - 1.0;
+  P.gM2 = ph->gamma * ph->mach * ph->mach;
+  P.Re = ph->reynolds;
+  P.invRe = 1.0 / ph->reynolds;
+  P.kcoef = 1.0 / ((ph->gamma - 1.0) * ph->prandtl * ph->mach * ph->mach);
+  P.suth = ph->sutherland;
+  P.suth1 = 1.0 + ph->sutherland;
+  P.cfl_adv = ph->cfl_adv;
+  P.cfl_visc = ph->cfl_visc;
+  P.pinf = 1.0 / (ph->gamma * ph->mach * ph->mach);
+  P.rhoE_inf = P.pinf / (ph->gamma - 1.0) + 0.5;
+  P.visc_const = ph->viscosity_model == 1;
+  P.family = ph->node_family;
+}
+
+// Mapping of one mesh raised to higher orders M' >= M (exact: its polynomial sampled at the new nodes).
+static void elevate_mapping(const pmg_mesh_s* m, const int Mn[3], std::vector<double>& out) {
+  const int M1 = m->M[0], M2 = m->M[1], M3 = m->M[2];
+  const size_t per_old = (size_t)(M1 + 1) * (M2 + 1) * (M3 + 1) * 3;
+  auto lag = [](int M, int a, double x) {
+    double v = 1.0;
+    for (int k = 0; k <= M; k++)
+      if (k != a) v *= (x - (-1.0 + 2.0 * k / M)) / ((-1.0 + 2.0 * a / M) - (-1.0 + 2.0 * k / M));
+    return v;
+  };
+  for (int64_t e = 0; e < m->K; e++) {
+    const double* g = m->gnodes.data() + e * per_old;
+    for (int k = 0; k <= Mn[2]; k++)
+      for (int j = 0; j <= Mn[1]; j++)
+        for (int i = 0; i <= Mn[0]; i++) {
+          double x[3] = {-1.0 + 2.0 * i / Mn[0], -1.0 + 2.0 * j / Mn[1], -1.0 + 2.0 * k / Mn[2]};
+          double p[3] = {0, 0, 0};
+          for (int c3 = 0; c3 <= M3; c3++)
+            for (int c2 = 0; c2 <= M2; c2++)
+              for (int c1 = 0; c1 <= M1; c1++) {
+                double wgt = lag(M1, c1, x[0]) * lag(M2, c2, x[1]) * lag(M3, c3, x[2]);
+                const double* q = g + ((c3 * (M2 + 1) + c2) * (M1 + 1) + c1) * 3;
+                for (int c = 0; c < 3; c++) p[c] += wgt * q[c];
+              }
+          for (int c = 0; c < 3; c++) out.push_back(p[c]);
+        }
+  }
+}
+
+static pmg_solver_s* create_solver(pmg_ctx ctx, const std::vector<const pmg_mesh_s*>& meshes,
+                                   const std::vector<const int32_t*>& orders, const pmg_physics* phys,
+                                   const pmg_mg_params* mg) {
+  REQUIRE(!meshes.empty(), "no problems");
+  HIPCHECK(hipSetDevice(ctx->device));
+  auto s = std::make_unique<pmg_solver_s>();
+  s->ctx = ctx;
+  const int n = (int)meshes.size();
+  s->nprob = n;
+  s->family = phys[0].node_family;
+  for (int p = 0; p < n; p++) {
+    REQUIRE(meshes[p] && orders[p], "NULL mesh or orders");
+    REQUIRE(meshes[p]->ctx == ctx, "mesh belongs to another context");
+    const pmg_physics* ph = &phys[p];
+    REQUIRE(ph->node_family == 0 || ph->node_family == 1, "node_family must be 0 or 1");
+    REQUIRE(ph->node_family == s->family, "every problem of a batch must use the same node family");
+    REQUIRE(ph->mach > 0 && ph->reynolds > 0 && ph->gamma > 1 && ph->prandtl > 0, "bad physics parameters");
+    REQUIRE(ph->cfl_adv > 0 && ph->cfl_visc > 0, "CFL constants must be positive");
+    Phys P;
+    set_phys(P, ph);
+    s->phys.push_back(P);
+  }
+  // the (union) mesh
+  if (n == 1) {
+    s->mesh = meshes[0];
+  } else {
+    auto um = std::make_unique<pmg_mesh_s>();
+    um->ctx = ctx;
+    um->K = 0;
+    for (int d = 0; d < 3; d++) {
+      um->M[d] = 1;
+      for (auto* m : meshes) um->M[d] = std::max(um->M[d], m->M[d]);
+    }
+    for (auto* m : meshes) {
+      int64_t base = um->K;
+      if (m->M[0] == um->M[0] && m->M[1] == um->M[1] && m->M[2] == um->M[2])
+        um->gnodes.insert(um->gnodes.end(), m->gnodes.begin(), m->gnodes.end());
+      else
+        elevate_mapping(m, um->M, um->gnodes);
+      for (int64_t v : m->nbr) um->nbr.push_back(v < 0 ? v : v + base);
+      um->nbrf.insert(um->nbrf.end(), m->nbrf.begin(), m->nbrf.end());
+      um->orient.insert(um->orient.end(), m->orient.begin(), m->orient.end());
+      um->bc.insert(um->bc.end(), m->bc.begin(), m->bc.end());
+      um->K += m->K;
+    }
+    REQUIRE(um->K < (1 << 30), "batch too large");
+    um->d_gnodes = um->arena.upload(um->gnodes);
+    s->own_mesh = std::move(um);
+    s->mesh = s->own_mesh.get();
+  }
+  const int K = (int)s->mesh->K;
+  s->prob_elem.push_back(0);
+  int pmax_first = -1;
+  for (int p = 0; p < n; p++) {
+    int pmax = 1;
+    for (int64_t e = 0; e < meshes[p]->K; e++)
+      for (int d = 0; d < 3; d++) {
+        int v = orders[p][3 * e + d];
+        REQUIRE(v >= 1 && v <= PMG_MAXN - 1, "orders must be 1..7");
+        s->orders.push_back(v);
+        pmax = std::max(pmax, v);
+      }
+    if (p == 0) pmax_first = pmax;
+    // equal maximum orders keep every problem's level sequence identical to its own solve
+    REQUIRE(pmax == pmax_first, "every problem of a batch must have the same maximum order");
+    for (int64_t e = 0; e < meshes[p]->K; e++) s->eprob.push_back(p);
+    s->prob_elem.push_back(s->prob_elem.back() + (int)meshes[p]->K);
+  }
+  s->nmax = pmax_first;
+  pmg_mg_params d;
+  memset(&d, 0, sizeof(d));
+  d.beta_pre = d.beta_post = d.beta_coarse = 3;
+  d.eta = 1.1;
+  d.max_repeats = 10;
+  d.fmg_threshold = 0.1;
+  s->mg = mg ? *mg : d;
+  REQUIRE(s->mg.beta_pre >= 0 && s->mg.beta_post >= 0 && s->mg.beta_coarse >= 0, "negative sweep count");
+  REQUIRE(!(n > 1 && s->mg.tuning), "residual-based smoothing tuning is per problem: not available in a batch");
+  s->d_ptab = s->arena.upload(s->phys);
+  s->d_eprob = s->arena.upload(s->eprob);
+  s->d_active = s->arena.upload(std::vector<int>(n, 1));
+  s->d_red = s->arena.alloc<unsigned long long>((size_t)NSLOTS * n);
+  s->top = build_level(s.get(), s->orders);
+  std::vector<int> caps;
+  if (mg && mg->n_levels > 0 && mg->level_caps) {
+    caps.assign(mg->level_caps, mg->level_caps + mg->n_levels);
+    for (size_t i = 1; i < caps.size(); i++) REQUIRE(caps[i] < caps[i - 1] && caps[i] >= 1, "level caps must decrease");
+  } else {
+    int nl = (mg && mg->n_levels > 0) ? mg->n_levels : s->nmax;
+    for (int c = s->nmax; c >= 1 && (int)caps.size() < nl; c--) caps.push_back(c);
+  }
+  s->mg.level_caps = nullptr;
+  build_hier(s.get(), s->iso, -1, caps);
+  size_t nq = 5 * (size_t)s->top->nn;
+  s->d_zero = s->arena.alloc<double>(nq);
+  s->d_R = s->arena.alloc<double>(nq);
+  s->d_G = s->arena.alloc<double>(nq);
+  k_fill<<<cdiv(nq, 256), 256>>>(s->d_zero, nq, 0.0);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipDeviceSynchronize());
+  (void)K;
+  return s.release();
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -781,7 +1077,6 @@ pmg_status pmg_mesh_create(pmg_ctx ctx, int64_t K, const int32_t M[3], const dou
         REQUIRE(h >= 0 && h < 6, "neighbour face out of range");
         REQUIRE(orient[6 * e + f] >= 0 && orient[6 * e + f] < 8, "orientation code out of range");
         REQUIRE(nbr_elem[6 * g + h] == e && nbr_face[6 * g + h] == f, "neighbour does not point back");
-        REQUIRE((h / 2 == f / 2) || true, "");
       }
     HIPCHECK(hipSetDevice(ctx->device));
     auto m = std::make_unique<pmg_mesh_s>();
@@ -805,59 +1100,17 @@ pmg_status pmg_solver_create(pmg_ctx ctx, pmg_mesh mesh, const int32_t* orders, 
                              const pmg_mg_params* mg, pmg_solver* out) {
   return guard([&] {
     REQUIRE(ctx && mesh && orders && ph && out, "NULL argument");
-    REQUIRE(mesh->ctx == ctx, "mesh belongs to another context");
-    REQUIRE(ph->node_family == 0 || ph->node_family == 1, "node_family must be 0 or 1");
-    REQUIRE(ph->mach > 0 && ph->reynolds > 0 && ph->gamma > 1 && ph->prandtl > 0, "bad physics parameters");
-    HIPCHECK(hipSetDevice(ctx->device));
-    auto s = std::make_unique<pmg_solver_s>();
-    s->ctx = ctx;
-    s->mesh = mesh;
-    const int K = (int)mesh->K;
-    s->orders.assign(orders, orders + 3 * K);
-    for (int v : s->orders) REQUIRE(v >= 1 && v <= PMG_MAXN - 1, "orders must be 1..7");
-    for (int v : s->orders) s->nmax = std::max(s->nmax, v);
-    Phys& P = s->phys;
-    P.gamma = ph->gamma;
-    P.gm1 = ph->gamma - 1.0;
-    P.gM2 = ph->gamma * ph->mach * ph->mach;
-    P.Re = ph->reynolds;
-    P.invRe = 1.0 / ph->reynolds;
-    P.kcoef = 1.0 / ((ph->gamma - 1.0) * ph->prandtl * ph->mach * ph->mach);
-    P.suth = ph->sutherland;
-    P.suth1 = 1.0 + ph->sutherland;
-    P.cfl_adv = ph->cfl_adv;
-    P.cfl_visc = ph->cfl_visc;
-    P.pinf = 1.0 / (ph->gamma * ph->mach * ph->mach);
-    P.rhoE_inf = P.pinf / (ph->gamma - 1.0) + 0.5;
-    P.visc_const = ph->viscosity_model == 1;
-    P.family = ph->node_family;
-    pmg_mg_params d;
-    memset(&d, 0, sizeof(d));
-    d.beta_pre = d.beta_post = d.beta_coarse = 3;
-    d.eta = 1.1;
-    d.max_repeats = 10;
-    d.fmg_threshold = 0.1;
-    s->mg = mg ? *mg : d;
-    REQUIRE(s->mg.beta_pre >= 0 && s->mg.beta_post >= 0 && s->mg.beta_coarse >= 0, "negative sweep count");
-    s->top = build_level(s.get(), s->orders);
-    std::vector<int> caps;
-    if (mg && mg->n_levels > 0 && mg->level_caps) {
-      caps.assign(mg->level_caps, mg->level_caps + mg->n_levels);
-      for (size_t i = 1; i < caps.size(); i++) REQUIRE(caps[i] < caps[i - 1] && caps[i] >= 1, "level caps must decrease");
-    } else {
-      int nl = (mg && mg->n_levels > 0) ? mg->n_levels : s->nmax;
-      for (int c = s->nmax; c >= 1 && (int)caps.size() < nl; c--) caps.push_back(c);
-    }
-    s->mg.level_caps = nullptr;
-    build_hier(s.get(), s->iso, -1, caps);
-    size_t n = 5 * (size_t)s->top->nn;
-    s->d_red = s->arena.alloc<unsigned long long>(NSLOTS);
-    s->d_zero = s->arena.alloc<double>(n);
-    s->d_R = s->arena.alloc<double>(n);
-    s->d_G = s->arena.alloc<double>(n);
-    HIPCHECK(hipMemset(s->d_zero, 0, n * sizeof(double)));
-    HIPCHECK(hipDeviceSynchronize());
-    *out = s.release();
+    *out = create_solver(ctx, {mesh}, {orders}, ph, mg);
+  });
+}
+
+pmg_status pmg_batch_create(pmg_ctx ctx, int n, const pmg_mesh* meshes, const int32_t* const* orders,
+                            const pmg_physics* phys, const pmg_mg_params* mg, pmg_solver* out) {
+  return guard([&] {
+    REQUIRE(ctx && meshes && orders && phys && out && n >= 1, "bad argument");
+    std::vector<const pmg_mesh_s*> ms(meshes, meshes + n);
+    std::vector<const int32_t*> os(orders, orders + n);
+    *out = create_solver(ctx, ms, os, phys, mg);
   });
 }
 
@@ -872,10 +1125,19 @@ pmg_status pmg_state_layout(pmg_solver s, int64_t* n_nodes, int64_t* elem_node_o
   });
 }
 
+pmg_status pmg_batch_layout(pmg_solver s, int* n_problems, int64_t* problem_node_offset) {
+  return guard([&] {
+    REQUIRE(s, "NULL solver");
+    if (n_problems) *n_problems = s->nprob;
+    if (problem_node_offset)
+      for (int p = 0; p <= s->nprob; p++) problem_node_offset[p] = s->top->off[s->prob_elem[p]];
+  });
+}
+
 pmg_status pmg_init_freestream(pmg_solver s, double* Q_dev, void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev, "NULL argument");
-    k_freestream<<<cdiv(s->top->nn, 256), 256, 0, (hipStream_t)stream>>>(s->phys, Q_dev, s->top->nn);
+    k_freestream<<<cdiv(s->top->nn, 256), 256, 0, (hipStream_t)stream>>>(s->top->dev, Q_dev);
     HIPCHECK(hipGetLastError());
   });
 }
@@ -895,12 +1157,26 @@ pmg_status pmg_residual(pmg_solver s, int op, const double* Q_dev, const double*
   });
 }
 
+pmg_status pmg_batch_norms(pmg_solver s, const double* Q_dev, const double* S_dev, double* res_inf_host,
+                           void* stream) {
+  return guard([&] {
+    REQUIRE(s && Q_dev && res_inf_host, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    residual(s, *s->top, Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
+    std::vector<double> v = read_slots(s, SLOT_NORM, st);
+    for (int p = 0; p < s->nprob; p++) res_inf_host[p] = v[p];
+  });
+}
+
 pmg_status pmg_timestep(pmg_solver s, const double* Q_dev, double* dt_host, void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && dt_host, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
     timestep(s, *s->top, Q_dev, st);
-    *dt_host = read_slot(s, SLOT_DT, st);
+    std::vector<double> v = read_slots(s, SLOT_DT, st);
+    double m = INFINITY;
+    for (double x : v) m = std::min(m, x);
+    *dt_host = m;
   });
 }
 
@@ -950,12 +1226,55 @@ pmg_status pmg_prolong(pmg_solver s, int hierarchy, int level, const double* Uc,
   });
 }
 
+pmg_status pmg_set_graph(pmg_solver s, int enable) {
+  return guard([&] {
+    REQUIRE(s, "NULL solver");
+    s->use_graph = enable ? 1 : 0;
+  });
+}
+
+pmg_status pmg_autotune(pmg_solver s, void* stream) {
+  return guard([&] {
+    REQUIRE(s, "NULL solver");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<Level*> done;
+    auto tune = [&](Hier& H) {
+      for (auto& l : H.lv)
+        if (std::find(done.begin(), done.end(), l.get()) == done.end()) {
+          autotune_level(s, *l, st);
+          done.push_back(l.get());
+        }
+    };
+    tune(s->iso);
+    for (int d = 0; d < 3; d++)
+      if (s->aniso[d]) tune(*s->aniso[d]);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);  // tiles changed: recapture
+    s->graphs.clear();
+    HIPCHECK(hipStreamSynchronize(st));
+  });
+}
+
+pmg_status pmg_level_tiles(pmg_solver s, int hierarchy, int level, int32_t* tile_target) {
+  return guard([&] {
+    REQUIRE(s && tile_target, "NULL argument");
+    Hier& H = pick_hier(s, hierarchy);
+    REQUIRE(level >= 0 && level < (int)H.lv.size(), "level out of range");
+    *tile_target = H.lv[level]->tile_target;
+  });
+}
+
 pmg_status pmg_vcycle(pmg_solver s, double* Q_dev, const double* S_dev, int n_cycles, double* res_inf_host,
                       void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && n_cycles >= 0, "bad argument");
     hipStream_t st = (hipStream_t)stream;
-    run_vcycles(s, s->iso, Q_dev, S_dev, n_cycles, nullptr, st);
+    if (s->use_graph && !s->mg.tuning && n_cycles > 0) {
+      // sources once eagerly, then the captured cycle (its sources are re-derived inside; identical work)
+      GraphKey key{0, Q_dev, S_dev, nullptr, 0};
+      run_graph(s, key, n_cycles, st, [&](hipStream_t cs) { run_vcycles(s, s->iso, Q_dev, S_dev, 1, nullptr, cs); });
+    } else {
+      run_vcycles(s, s->iso, Q_dev, S_dev, n_cycles, nullptr, st);
+    }
     HIPCHECK(hipGetLastError());
     if (res_inf_host) {
       residual(s, *s->top, Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
@@ -1011,19 +1330,64 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
   return rc;
 }
 
+pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, double tol, int max_cycles,
+                           int32_t* cycles_out, double* res_inf_out, void* stream) {
+  pmg_status rc = guard([&] {
+    REQUIRE(s && Q_dev && max_cycles >= 0, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int n = s->nprob;
+    std::vector<int> active(n, 1), cyc(n, 0);
+    std::vector<double> r(n, 0.0);
+    bool done = false;
+    for (int k = 0;; k++) {
+      residual(s, *s->top, Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
+      r = read_slots(s, SLOT_NORM, st);
+      int nact = 0;
+      for (int p = 0; p < n; p++) {
+        if (r[p] != r[p]) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual in problem " + std::to_string(p));
+        if (active[p] && (r[p] < tol || cyc[p] >= max_cycles)) active[p] = 0;  // converged problems freeze
+        nact += active[p];
+      }
+      if (nact == 0) {
+        done = true;
+        break;
+      }
+      HIPCHECK(hipMemcpyAsync(s->d_active, active.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+      if (s->use_graph) {
+        GraphKey key{0, Q_dev, S_dev, nullptr, 0};
+        run_graph(s, key, 1, st, [&](hipStream_t cs) { run_vcycles(s, s->iso, Q_dev, S_dev, 1, nullptr, cs); });
+      } else {
+        run_vcycles(s, s->iso, Q_dev, S_dev, 1, nullptr, st);
+      }
+      for (int p = 0; p < n; p++) cyc[p] += active[p];
+    }
+    std::vector<int> ones(n, 1);
+    HIPCHECK(hipMemcpy(s->d_active, ones.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    bool all = true;
+    for (int p = 0; p < n; p++) {
+      if (cycles_out) cycles_out[p] = cyc[p];
+      if (res_inf_out) res_inf_out[p] = r[p];
+      all = all && r[p] < tol;
+    }
+    (void)done;
+    if (!all) throw PmgError(PMG_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance in some problem");
+  });
+  return rc;
+}
+
 pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, int isolated, double* tau_map_dev,
                             void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && tau_map_dev, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
     const int nt = std::max(s->nmax - 1, 1);
-    size_t n = (size_t)s->mesh->K * 3 * nt;
-    k_fill<<<cdiv(n, 256), 256, 0, st>>>(tau_map_dev, n, NAN);
     TauRec tau{tau_map_dev, nt, isolated ? 1 : 0};
-    for (int d = 0; d < 3; d++) {
-      Hier& H = aniso_hier(s, d);
-      if (H.lv.size() < 2) continue;
-      run_vcycles(s, H, Q_dev, S_dev, 1, &tau, st);
+    for (int d = 0; d < 3; d++) aniso_hier(s, d);  // built before any capture
+    if (s->use_graph) {
+      GraphKey key{1, Q_dev, S_dev, tau_map_dev, tau.isolated};
+      run_graph(s, key, 1, st, [&](hipStream_t cs) { tau_cycles(s, Q_dev, S_dev, tau, cs); });
+    } else {
+      tau_cycles(s, Q_dev, S_dev, tau, st);
     }
     HIPCHECK(hipGetLastError());
   });

@@ -486,6 +486,37 @@ def config_plate(nx: int = 64, ny: int = 32, N=(6, 6, 1), seed: int = 2, amp: fl
     return Workload(f"plate{nx}x{ny}_N{N[0]}{N[1]}{N[2]}", mesh, orders, phys, Q)
 
 
+def config_batch(n: int = 64, kmin: int = 2000, kmax: int = 20000, seed: int = 4, lo: int = 2, hi: int = 5,
+                 amp: float = 1e-3):
+    """Independent steady problems: random boxes of kmin..kmax hexes (split into nx x ny x nz by seeded aspect
+    draws), stretched toward a y = 0 no-slip wall by a ratio in [1, 1.15], far field on the other x / y
+    sides, periodic in z, trilinear mapping; orders iid in [lo, hi] per direction (the maximum hi is present
+    in every problem); Mach in [0.1, 0.4] and Re in [1e2, 1e4], all from the seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(n):
+        K = int(rng.integers(kmin, kmax + 1))
+        a = rng.uniform(0.5, 2.0, size=3)
+        nz = max(1, int(round((K / (a[0] * a[1])) ** (1 / 3) * a[2] ** 0)))
+        base = max(1, int(round((K / nz) ** 0.5)))
+        nx = max(1, int(round(base * a[0] / a[1])))
+        ny = max(1, int(round(K / (nx * nz))))
+        ratio = float(rng.uniform(1.0, 1.15))
+        mesh = box_mesh((nx, ny, nz), (0.0, 0.0, 0.0), (1.0 * nx / max(nx, ny), 1.0 * ny / max(nx, ny), 0.1 * nz),
+                        M=(1, 1, 1), periodic=(False, False, True), ratio=(1.0, ratio, 1.0),
+                        bc_lo=(BC_FARFIELD, BC_WALL, BC_NONE), bc_hi=(BC_FARFIELD, BC_FARFIELD, BC_NONE),
+                        name=f"batch{p}")
+        orders = rng.integers(lo, hi + 1, size=(mesh.K, 3)).astype(np.int32)
+        orders[int(rng.integers(0, mesh.K)), :] = hi
+        mach = float(rng.uniform(0.1, 0.4))
+        re = float(rng.uniform(1e2, 1e4))
+        phys = Physics(mach=mach, reynolds=re, family=FAMILY_LG, cfl_adv=0.2, cfl_visc=0.2)
+        n_nodes = int(node_offsets(orders)[-1])
+        Q = perturbed_freestream(n_nodes, mach, amp, seed * 1000 + p)
+        out.append(Workload(f"batch{p}_{nx}x{ny}x{nz}", mesh, orders, phys, Q))
+    return out
+
+
 def config_ogrid(nt: int = 8, nr: int = 13, seed: int = 3, lo: int = 1, hi: int = 7, amp: float = 1e-3,
                  r_out: float = 20.0, ratio: float = 1.25, cfl: float = 0.2) -> Workload:
     """Six-block O-grid around the unit sphere (outer radius 20), quadratic mapping, iid orders in [lo,hi].

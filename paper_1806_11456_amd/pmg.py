@@ -23,7 +23,9 @@ STATUS = {0: "PMG_OK", 1: "PMG_ERR_INVALID_ARG", 2: "PMG_ERR_OOM", 3: "PMG_ERR_H
 EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_create", "pmg_mesh_destroy",
            "pmg_solver_create", "pmg_solver_destroy", "pmg_state_layout", "pmg_init_freestream", "pmg_residual",
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
-           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read"]
+           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_batch_create",
+           "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
+           "pmg_level_tiles"]
 
 # kernel kinds of pmg_profile_enable / pmg_profile_read
 KINDS = {"trace": 0, "face1": 1, "grad": 2, "face2": 3, "div": 4, "dt": 5, "transfer": 6}
@@ -94,6 +96,14 @@ def lib():
     L.pmg_tau_estimate.argtypes = [P, V, V, C.c_int, V, V]
     L.pmg_profile_enable.argtypes = [P, C.c_uint32]
     L.pmg_profile_read.argtypes = [P, C.c_int, D, I64, D]
+    L.pmg_batch_create.argtypes = [P, C.c_int, C.POINTER(C.c_void_p), C.POINTER(I32), C.POINTER(Physics),
+                                   C.POINTER(MGParams), pp]
+    L.pmg_batch_layout.argtypes = [P, I32, I64]
+    L.pmg_batch_norms.argtypes = [P, V, V, D, V]
+    L.pmg_batch_solve.argtypes = [P, V, V, C.c_double, C.c_int, I32, D, V]
+    L.pmg_set_graph.argtypes = [P, C.c_int]
+    L.pmg_autotune.argtypes = [P, V]
+    L.pmg_level_tiles.argtypes = [P, C.c_int, C.c_int, I32]
     for name in EXPORTS:
         if name not in ("pmg_last_error", "pmg_ctx_destroy", "pmg_mesh_destroy", "pmg_solver_destroy"):
             getattr(L, name).restype = C.c_int
@@ -163,25 +173,31 @@ class Solver:
     """mesh + orders + physics + multigrid hierarchy on one GPU."""
 
     def __init__(self, ctx: Context, mesh: Mesh, orders, phys, mg: MG = MG()):
-        import torch
-        self.ctx, self.mesh, self.phys, self.mg = ctx, mesh, phys, mg
-        self.torch = torch
-        self.device = torch.device("cuda", ctx.device)
         orders = np.ascontiguousarray(orders, dtype=np.int32)
-        self.orders = orders
-        caps = None if mg.level_caps is None else np.asarray(mg.level_caps, dtype=np.int32)
-        self._caps = caps
-        p = MGParams(0 if caps is None else len(caps),
-                     None if caps is None else caps.ctypes.data_as(C.POINTER(C.c_int32)),
-                     mg.beta_pre, mg.beta_post, mg.beta_coarse, mg.tuning, mg.eta, mg.max_repeats, mg.fmg,
-                     mg.fmg_threshold)
+        p = self._params(mg)
         ph = physics_struct(phys)
         h = C.c_void_p()
         _check(lib().pmg_solver_create(ctx.h, mesh.h, orders.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(ph),
                                        C.byref(p), C.byref(h)))
-        self.h = h
+        self._setup(ctx, h, mesh.K, orders, mg)
+        self.mesh, self.phys = mesh, phys
+
+    def _params(self, mg):
+        caps = None if mg.level_caps is None else np.asarray(mg.level_caps, dtype=np.int32)
+        self._caps = caps
+        return MGParams(0 if caps is None else len(caps),
+                        None if caps is None else caps.ctypes.data_as(C.POINTER(C.c_int32)),
+                        mg.beta_pre, mg.beta_post, mg.beta_coarse, mg.tuning, mg.eta, mg.max_repeats, mg.fmg,
+                        mg.fmg_threshold)
+
+    def _setup(self, ctx, h, K, orders, mg):
+        import torch
+        self.ctx, self.mg, self.h, self.K = ctx, mg, h, K
+        self.torch = torch
+        self.device = torch.device("cuda", ctx.device)
+        self.orders = orders
         nn = C.c_int64()
-        off = np.zeros(mesh.K + 1, dtype=np.int64)
+        off = np.zeros(K + 1, dtype=np.int64)
         _check(lib().pmg_state_layout(h, C.byref(nn), off.ctypes.data_as(C.POINTER(C.c_int64))))
         self.n_nodes = int(nn.value)
         self.offsets = off
@@ -227,7 +243,7 @@ class Solver:
         if level < 0:
             _check(lib().pmg_level_info(self.h, hierarchy, -1, C.byref(nl), None, None))
             return int(nl.value)
-        orders = np.zeros((self.mesh.K, 3), dtype=np.int32)
+        orders = np.zeros((self.K, 3), dtype=np.int32)
         _check(lib().pmg_level_info(self.h, hierarchy, level, C.byref(nl), C.byref(nn),
                                     orders.ctypes.data_as(C.POINTER(C.c_int32))))
         return int(nn.value), orders
@@ -274,6 +290,58 @@ class Solver:
 
     def tau_estimate(self, Q, S=None, isolated=True):
         nt = max(self.nmax - 1, 1)
-        tau = self.torch.empty((self.mesh.K, 3, nt), dtype=self.torch.float64, device=self.device)
+        tau = self.torch.empty((self.K, 3, nt), dtype=self.torch.float64, device=self.device)
         _check(lib().pmg_tau_estimate(self.h, _ptr(Q), _ptr(S), int(bool(isolated)), _ptr(tau), _stream()))
         return tau
+
+    def set_graph(self, enable: bool):
+        _check(lib().pmg_set_graph(self.h, int(bool(enable))))
+
+    def autotune(self):
+        _check(lib().pmg_autotune(self.h, _stream()))
+
+    def level_tiles(self, hierarchy: int, level: int) -> int:
+        t = C.c_int32()
+        _check(lib().pmg_level_tiles(self.h, hierarchy, level, C.byref(t)))
+        return int(t.value)
+
+
+class Batch(Solver):
+    """n independent problems advanced together (one union solver; per-problem step, norms, freezing)."""
+
+    def __init__(self, ctx: Context, meshes, orders_list, phys_list, mg: MG = MG()):
+        n = len(meshes)
+        ords = [np.ascontiguousarray(o, dtype=np.int32) for o in orders_list]
+        self._ords = ords
+        mesh_arr = (C.c_void_p * n)(*[m.h.value for m in meshes])
+        ord_arr = (C.POINTER(C.c_int32) * n)(*[o.ctypes.data_as(C.POINTER(C.c_int32)) for o in ords])
+        ph_arr = (Physics * n)(*[physics_struct(p) for p in phys_list])
+        p = self._params(mg)
+        h = C.c_void_p()
+        _check(lib().pmg_batch_create(ctx.h, n, mesh_arr, ord_arr, ph_arr, C.byref(p), C.byref(h)))
+        K = sum(m.K for m in meshes)
+        self._setup(ctx, h, K, np.concatenate(ords), mg)
+        self.meshes, self.phys_list, self.n = meshes, phys_list, n
+        npb = C.c_int32()
+        off = np.zeros(n + 1, dtype=np.int64)
+        _check(lib().pmg_batch_layout(h, C.byref(npb), off.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.problem_offsets = off
+
+    def norms(self, Q, S=None):
+        r = np.zeros(self.n)
+        _check(lib().pmg_batch_norms(self.h, _ptr(Q), _ptr(S), r.ctypes.data_as(C.POINTER(C.c_double)), _stream()))
+        return r
+
+    def solve_all(self, Q, S=None, tol=1e-9, max_cycles=100, raise_not_converged=True):
+        cyc = np.zeros(self.n, dtype=np.int32)
+        r = np.zeros(self.n)
+        rc = lib().pmg_batch_solve(self.h, _ptr(Q), _ptr(S), float(tol), int(max_cycles),
+                                   cyc.ctypes.data_as(C.POINTER(C.c_int32)), r.ctypes.data_as(C.POINTER(C.c_double)),
+                                   _stream())
+        if rc != 0 and (rc != 5 or raise_not_converged):
+            _check(rc)
+        return cyc, r
+
+    def part(self, U, p: int):
+        """View of problem p's nodes in a batch array [5][n_nodes]."""
+        return U[:, int(self.problem_offsets[p]):int(self.problem_offsets[p + 1])]
