@@ -84,6 +84,16 @@ typedef struct {
   int32_t max_repeats;       /* cap on tuning repetitions per smoothing phase */
   int32_t fmg;               /* 1: pmg_solve starts with a full-multigrid ramp */
   double fmg_threshold;      /* residual that raises the FMG level (1e-1 plate, 1.0 sphere) */
+  int32_t precision;         /* 0: every level in FP64.  1: mixed precision, with the isotropic levels below the
+                                finest smoothed in FP32.  Their state Q~ is the FP64 restriction rounded once;
+                                their FAS source is A(Q~) + r formed by the same FP32 operator, so Q~ = Q~0
+                                leaves exactly r.  Their correction Q~ - Q~0 is taken in FP32 and added in FP64.
+                                The finest level, its residual, the stopping test and the truncation-error
+                                hierarchies stay FP64.  pmg_solve / pmg_batch_solve switch a problem to FP64
+                                coarse levels once its FP64 residual stops reaching new minima (the round-off
+                                floor of the FP32 correction), so the converged solution is an FP64 solution. */
+  int32_t mixed_patience;    /* precision 1: cycles without a new minimum of the residual before the switch
+                                (0 = 4) */
 } pmg_mg_params;
 
 const char* pmg_last_error(void);
@@ -197,10 +207,16 @@ pmg_status pmg_batch_layout(pmg_solver s, int* n_problems, int64_t* problem_node
 /* res_inf_host: host, n entries, max |S - A(Q)| of each problem (waits for the stream). */
 pmg_status pmg_batch_norms(pmg_solver s, const double* Q_dev, const double* S_dev, double* res_inf_host,
                            void* stream);
-/* V-cycles until every problem is below tol; a converged problem is frozen (its RK updates take a zero
- * step, so its state no longer changes) while the others continue.  cycles_out / res_inf_out: n entries. */
+/* V-cycles until every problem is below tol; a converged problem is frozen (the tiles of its elements and
+ * faces skip the cycle's work, so its state no longer changes) while the others continue.  With mixed
+ * precision, problems on FP32 coarse levels and problems already switched to FP64 ones advance in two
+ * cycles per iteration, each skipping the other set.  cycles_out / res_inf_out: n entries. */
 pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, double tol, int max_cycles,
                            int32_t* cycles_out, double* res_inf_out, void* stream);
+/* Mixed precision (pmg_mg_params.precision = 1, Sec. 3.1 cycle with FP32 coarse levels): fp32_cycles (host,
+ * one entry per problem) receives the number of cycles of the last pmg_solve / pmg_batch_solve that ran
+ * with FP32 coarse levels before the switch to FP64 ones (0 for an FP64 solver). */
+pmg_status pmg_solve_stats(pmg_solver s, int32_t* fp32_cycles);
 
 /*
  * Graph mode: with enable = 1, pmg_vcycle, pmg_batch_solve (cycles) and pmg_tau_estimate replay a HIP graph

@@ -1,5 +1,7 @@
 // Device-side building blocks: basis tables in constant memory, level descriptors, and the pointwise
 // physics of the compressible Navier-Stokes equations (paper, Appendix A) with the Roe flux (Sec. 2).
+// Operator kernels are templated on the working precision T (double on the fine level and for the
+// truncation error; float on the coarse levels of the mixed-precision cycle).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -49,59 +51,71 @@ struct FaceRec {
   int flags;           // bit0 master side equals the mortar, bit1 slave side equals the mortar
 };
 
-struct LevelDev {
+// One discretisation level as the kernels see it; geometry arrays in the working precision T.
+template <class T>
+struct LevelDevT {
   int K, nn, nf, nm, fam;
-  const Phys* __restrict__ ptab;   // physics of each problem of the batch
-  const int* __restrict__ eprob;   // problem of each element
+  const Phys* __restrict__ ptab;      // physics of each problem of the batch
+  const int* __restrict__ eprob;      // problem of each element
   const int* __restrict__ node_elem;  // element of each node
-  const double* __restrict__ dt;   // per-problem explicit step (device scalars, read by the RK epilogue)
-  const int* __restrict__ active;  // per-problem: 0 = frozen (its RK updates use a zero step)
-  const int* __restrict__ ord;   // K*3 orders
-  const int* __restrict__ off;   // K+1 node offsets
-  const int* __restrict__ fo;    // K*6 face-node offsets
-  const double* __restrict__ Ja;   // [9][nn]  (J a^d)_c at [(d*3 + c)]
-  const double* __restrict__ invJ; // [nn]
-  const double* __restrict__ J;    // [nn]
-  const double* __restrict__ Nout; // [3][nf] outward normal x surface Jacobian, own side
-  const int4* __restrict__ tiles;  // {first, count, packed n1|n2<<8|n3<<16, nodes}
+  const double* __restrict__ dt;      // per-problem explicit step (read by the RK epilogue)
+  const int* __restrict__ active;     // per-problem: 0 = frozen (its RK updates use a zero step)
+  const int* __restrict__ skip;       // nullable; tiles of problems p with skip[p] == 0 return at once
+  const int* __restrict__ ord;        // K*3 orders
+  const int* __restrict__ off;        // K+1 node offsets
+  const int* __restrict__ fo;         // K*6 face-node offsets
+  const T* __restrict__ Ja;           // [9][nn]  (J a^d)_c at [(d*3 + c)]
+  const T* __restrict__ invJ;         // [nn]
+  const T* __restrict__ J;            // [nn]
+  const T* __restrict__ Nout;         // [3][nf] outward normal x surface Jacobian, own side
+  const int4* __restrict__ tiles;     // {first, count, packed n1|n2<<8|n3<<16, nodes}
   const int* __restrict__ elist;
   const FaceRec* __restrict__ faces;
-  const int* __restrict__ mface;   // mortar node -> face
-  const int* __restrict__ ftile;   // face tile boundaries in mortar nodes
-  const double* __restrict__ mgeo; // [4][nm] unit normal (master outward) and surface Jacobian
-  const double* __restrict__ T;    // transfer tables of this family
+  const int* __restrict__ mface;      // mortar node -> face
+  const int* __restrict__ ftile;      // face tile boundaries in mortar nodes
+  const T* __restrict__ mgeo;         // [4][nm] unit normal (master outward) and surface Jacobian
+  const double* __restrict__ T_;      // transfer tables of this family
 };
+using LevelDev = LevelDevT<double>;
+
+// Dynamic LDS of a templated kernel, viewed in its working type.
+#define PMG_DYN_LDS(T, name)                             \
+  extern __shared__ __align__(16) unsigned char name##_raw[]; \
+  T* name = reinterpret_cast<T*>(name##_raw)
 
 // ------------------------------------------------------------------------------------------------
 // Pointwise physics
 // ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ void prim(const Phys& P, const double q[5], double& rho, double v[3], double& p,
-                                     double& T) {
+template <class T>
+__device__ __forceinline__ void prim(const Phys& P, const T q[5], T& rho, T v[3], T& p, T& Tt) {
   rho = q[0];
-  double ir = 1.0 / q[0];
+  T ir = T(1) / q[0];
   v[0] = q[1] * ir;
   v[1] = q[2] * ir;
   v[2] = q[3] * ir;
-  p = P.gm1 * (q[4] - 0.5 * (q[1] * v[0] + q[2] * v[1] + q[3] * v[2]));
-  T = P.gM2 * p * ir;
+  p = T(P.gm1) * (q[4] - T(0.5) * (q[1] * v[0] + q[2] * v[1] + q[3] * v[2]));
+  Tt = T(P.gM2) * p * ir;
 }
 
-__device__ __forceinline__ double mu_of(const Phys& P, double T) {
-  if (P.visc_const) return 1.0;
-  return T * sqrt(T) * P.suth1 / (T + P.suth);
+template <class T>
+__device__ __forceinline__ T mu_of(const Phys& P, T Tt) {
+  if (P.visc_const) return T(1);
+  return Tt * sqrt(Tt) * T(P.suth1) / (Tt + T(P.suth));
 }
 
-__device__ __forceinline__ void prim_w(const Phys& P, const double q[5], double W[4]) {
-  double rho, v[3], p, T;
-  prim(P, q, rho, v, p, T);
-  W[0] = v[0]; W[1] = v[1]; W[2] = v[2]; W[3] = T;
+template <class T>
+__device__ __forceinline__ void prim_w(const Phys& P, const T q[5], T W[4]) {
+  T rho, v[3], p, Tt;
+  prim(P, q, rho, v, p, Tt);
+  W[0] = v[0]; W[1] = v[1]; W[2] = v[2]; W[3] = Tt;
 }
 
 // F^a . N for an arbitrary vector N (5 components)
-__device__ __forceinline__ void flux_adv_n(const Phys& P, const double q[5], const double N[3], double out[5]) {
-  double rho, v[3], p, T;
-  prim(P, q, rho, v, p, T);
-  double vn = v[0] * N[0] + v[1] * N[1] + v[2] * N[2];
+template <class T>
+__device__ __forceinline__ void flux_adv_n(const Phys& P, const T q[5], const T N[3], T out[5]) {
+  T rho, v[3], p, Tt;
+  prim(P, q, rho, v, p, Tt);
+  T vn = v[0] * N[0] + v[1] * N[1] + v[2] * N[2];
   out[0] = q[0] * vn;
   out[1] = q[1] * vn + p * N[0];
   out[2] = q[2] * vn + p * N[1];
@@ -111,91 +125,86 @@ __device__ __forceinline__ void flux_adv_n(const Phys& P, const double q[5], con
 
 // Viscous flux tensor F^v[c][v] (row v = 0 is zero and not stored: F[c][0..3] = momentum, energy)
 // g[k*3 + c] = dW_k / dx_c, W = (u, v, w, T).  wall: no-slip adiabatic wall flux (no work, no heat flux).
-__device__ __forceinline__ void flux_visc(const Phys& P, const double q[5], const double g[12], bool wall,
-                                          double F[3][4]) {
-  double rho, v[3], p, T;
-  prim(P, q, rho, v, p, T);
-  double mu = mu_of(P, T);
-  double div = g[0] + g[4] + g[8];
-  double lam = -2.0 / 3.0 * mu * div;
-  double tau[3][3];
+template <class T>
+__device__ __forceinline__ void flux_visc(const Phys& P, const T q[5], const T g[12], bool wall, T F[3][4]) {
+  T rho, v[3], p, Tt;
+  prim(P, q, rho, v, p, Tt);
+  T mu = mu_of(P, Tt);
+  T div = g[0] + g[4] + g[8];
+  T lam = T(-2.0 / 3.0) * mu * div;
+  T tau[3][3];
 #pragma unroll
   for (int i = 0; i < 3; i++)
 #pragma unroll
     for (int j = 0; j < 3; j++) tau[i][j] = mu * (g[i * 3 + j] + g[j * 3 + i]);
   tau[0][0] += lam; tau[1][1] += lam; tau[2][2] += lam;
-  double kap = mu * P.kcoef;
+  T kap = mu * T(P.kcoef);
+  const T invRe = T(P.invRe);
 #pragma unroll
   for (int c = 0; c < 3; c++) {
-    F[c][0] = P.invRe * tau[c][0];
-    F[c][1] = P.invRe * tau[c][1];
-    F[c][2] = P.invRe * tau[c][2];
-    F[c][3] = wall ? 0.0 : P.invRe * (v[0] * tau[c][0] + v[1] * tau[c][1] + v[2] * tau[c][2] + kap * g[9 + c]);
+    F[c][0] = invRe * tau[c][0];
+    F[c][1] = invRe * tau[c][1];
+    F[c][2] = invRe * tau[c][2];
+    F[c][3] = wall ? T(0) : invRe * (v[0] * tau[c][0] + v[1] * tau[c][1] + v[2] * tau[c][2] + kap * g[9 + c]);
   }
 }
 
 // Roe flux along the unit normal n (from L to R), standard Roe averages, no entropy fix.
-__device__ __forceinline__ void roe_flux(const Phys& P, const double qL[5], const double qR[5], const double n[3],
-                                         double Fn[5]) {
-  double rL, vL[3], pL, TL, rR, vR[3], pR, TR;
+template <class T>
+__device__ __forceinline__ void roe_flux(const Phys& P, const T qL[5], const T qR[5], const T n[3], T Fn[5]) {
+  T rL, vL[3], pL, TL, rR, vR[3], pR, TR;
   prim(P, qL, rL, vL, pL, TL);
   prim(P, qR, rR, vR, pR, TR);
-  double HL = (qL[4] + pL) / rL, HR = (qR[4] + pR) / rR;
-  double sL = sqrt(rL), sR = sqrt(rR);
-  double isum = 1.0 / (sL + sR);
-  double rh = sL * sR;
-  double vh[3] = {(sL * vL[0] + sR * vR[0]) * isum, (sL * vL[1] + sR * vR[1]) * isum, (sL * vL[2] + sR * vR[2]) * isum};
-  double Hh = (sL * HL + sR * HR) * isum;
-  double v2 = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
-  double c2 = P.gm1 * (Hh - 0.5 * v2);
-  double ch = sqrt(c2);
-  double un = vh[0] * n[0] + vh[1] * n[1] + vh[2] * n[2];
-  double dr = rR - rL, dp = pR - pL;
-  double dv[3] = {vR[0] - vL[0], vR[1] - vL[1], vR[2] - vL[2]};
-  double dun = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
-  double i2c2 = 1.0 / (2.0 * c2);
-  double a1 = (dp - rh * ch * dun) * i2c2;
-  double a5 = (dp + rh * ch * dun) * i2c2;
-  double a2 = dr - dp / c2;
-  double l1 = fabs(un - ch), l5 = fabs(un + ch), l2 = fabs(un);
-  double d[5];
+  T HL = (qL[4] + pL) / rL, HR = (qR[4] + pR) / rR;
+  T sL = sqrt(rL), sR = sqrt(rR);
+  T isum = T(1) / (sL + sR);
+  T rh = sL * sR;
+  T vh[3] = {(sL * vL[0] + sR * vR[0]) * isum, (sL * vL[1] + sR * vR[1]) * isum, (sL * vL[2] + sR * vR[2]) * isum};
+  T Hh = (sL * HL + sR * HR) * isum;
+  T v2 = vh[0] * vh[0] + vh[1] * vh[1] + vh[2] * vh[2];
+  T c2 = T(P.gm1) * (Hh - T(0.5) * v2);
+  T ch = sqrt(c2);
+  T un = vh[0] * n[0] + vh[1] * n[1] + vh[2] * n[2];
+  T dr = rR - rL, dp = pR - pL;
+  T dv[3] = {vR[0] - vL[0], vR[1] - vL[1], vR[2] - vL[2]};
+  T dun = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
+  T i2c2 = T(1) / (T(2) * c2);
+  T a1 = (dp - rh * ch * dun) * i2c2;
+  T a5 = (dp + rh * ch * dun) * i2c2;
+  T a2 = dr - dp / c2;
+  T l1 = fabs(un - ch), l5 = fabs(un + ch), l2 = fabs(un);
+  T d[5];
   d[0] = l1 * a1 + l5 * a5 + l2 * a2;
 #pragma unroll
   for (int c = 0; c < 3; c++)
     d[1 + c] = l1 * a1 * (vh[c] - ch * n[c]) + l5 * a5 * (vh[c] + ch * n[c]) + l2 * a2 * vh[c] +
                l2 * rh * (dv[c] - dun * n[c]);
-  d[4] = l1 * a1 * (Hh - un * ch) + l5 * a5 * (Hh + un * ch) + l2 * a2 * 0.5 * v2 +
+  d[4] = l1 * a1 * (Hh - un * ch) + l5 * a5 * (Hh + un * ch) + l2 * a2 * T(0.5) * v2 +
          l2 * rh * (vh[0] * dv[0] + vh[1] * dv[1] + vh[2] * dv[2] - un * dun);
-  double fl[5], fr[5];
+  T fl[5], fr[5];
   flux_adv_n(P, qL, n, fl);
   flux_adv_n(P, qR, n, fr);
 #pragma unroll
-  for (int k = 0; k < 5; k++) Fn[k] = 0.5 * (fl[k] + fr[k]) - 0.5 * d[k];
+  for (int k = 0; k < 5; k++) Fn[k] = T(0.5) * (fl[k] + fr[k]) - T(0.5) * d[k];
 }
 
-__device__ __forceinline__ void freestream(const Phys& P, double q[5]) {
-  q[0] = 1.0; q[1] = 1.0; q[2] = 0.0; q[3] = 0.0; q[4] = P.rhoE_inf;
+template <class T>
+__device__ __forceinline__ void freestream(const Phys& P, T q[5]) {
+  q[0] = T(1); q[1] = T(1); q[2] = T(0); q[3] = T(0); q[4] = T(P.rhoE_inf);
 }
 
 // ghost state of a boundary node (unit outward normal n)
-__device__ __forceinline__ void ghost_state(const Phys& P, int bc, const double q[5], const double n[3], double g[5]) {
+template <class T>
+__device__ __forceinline__ void ghost_state(const Phys& P, int bc, const T q[5], const T n[3], T g[5]) {
   if (bc == 1) {
     g[0] = q[0]; g[1] = -q[1]; g[2] = -q[2]; g[3] = -q[3]; g[4] = q[4];
   } else if (bc == 3) {
-    double mn = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
-    g[0] = q[0]; g[1] = q[1] - 2.0 * mn * n[0]; g[2] = q[2] - 2.0 * mn * n[1]; g[3] = q[3] - 2.0 * mn * n[2];
+    T mn = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
+    g[0] = q[0]; g[1] = q[1] - T(2) * mn * n[0]; g[2] = q[2] - T(2) * mn * n[1]; g[3] = q[3] - T(2) * mn * n[2];
     g[4] = q[4];
   } else {
     freestream(P, g);
   }
-}
-
-// non-negative doubles order like their bit patterns
-__device__ __forceinline__ void atomic_max_pos(unsigned long long* a, double v) {
-  atomicMax(a, (unsigned long long)__double_as_longlong(v));
-}
-__device__ __forceinline__ void atomic_min_pos(unsigned long long* a, double v) {
-  atomicMin(a, (unsigned long long)__double_as_longlong(v));
 }
 
 __device__ __forceinline__ void unpack3(int p, int& n1, int& n2, int& n3) {

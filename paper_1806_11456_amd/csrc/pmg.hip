@@ -11,6 +11,7 @@
 #include <stdexcept>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pmg.h"
@@ -111,8 +112,17 @@ struct pmg_mesh_s {
   double* d_gnodes = nullptr;
 };
 
+enum { PREC_F64 = 0, PREC_F32 = 1 };
+
+// Work arrays of the operator stages in a level's precision.
+template <class T>
+struct Work {
+  T *qf = nullptr, *Ws = nullptr, *gW = nullptr, *gf = nullptr, *PhiA = nullptr, *Phi = nullptr;
+};
+
 struct Level {
   int K = 0, nn = 0, nf = 0, nm = 0, fam = 0;
+  int prec = PREC_F64;  // working precision of the operator and smoother on this level
   std::vector<int> ord, off, fo;
   int ntiles = 0, nftiles = 0, max_tile = 0, tile_target = 256;
   DevArena arena;
@@ -120,12 +130,23 @@ struct Level {
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile;
   int4* d_tiles;
   FaceRec* d_faces;
-  double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;
-  double *d_qf, *d_Ws, *d_gW, *d_gf, *d_PhiA, *d_Phi;
-  LevelDev dev;
-  size_t lds_trace() const { return (size_t)5 * max_tile * sizeof(double); }
-  size_t lds_grad() const { return (size_t)13 * max_tile * sizeof(double); }
-  size_t lds_div() const { return (size_t)15 * max_tile * sizeof(double); }
+  double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;  // geometry in FP64 (always kept)
+  Work<double> w64;
+  Work<float> w32;
+  LevelDevT<double> dev;
+  LevelDevT<float> dev32;  // FP32 copies of the geometry (FP32 levels)
+  template <class T>
+  const LevelDevT<T>& devT() const {
+    if constexpr (std::is_same<T, float>::value) return dev32; else return dev;
+  }
+  template <class T>
+  const Work<T>& work() const {
+    if constexpr (std::is_same<T, float>::value) return w32; else return w64;
+  }
+  size_t wsize() const { return prec == PREC_F32 ? sizeof(float) : sizeof(double); }
+  size_t lds_trace() const { return (size_t)5 * max_tile * wsize(); }
+  size_t lds_grad() const { return (size_t)13 * max_tile * wsize(); }
+  size_t lds_div() const { return (size_t)15 * max_tile * wsize(); }
 };
 
 struct XferTiles {
@@ -140,7 +161,7 @@ struct Hier {
   int dir = -1;
   std::vector<std::shared_ptr<Level>> lv;  // 0 = coarsest
   std::vector<int> caps;                   // per level index
-  std::vector<double*> Q, Q0, S, r, Sp, G, R;
+  std::vector<void*> Q, Q0, S, r, Sp, G, R;  // [5][nn] per level, in that level's precision
   std::vector<std::unique_ptr<XferTiles>> xf;  // xf[l]: pair (l, l+1)
   DevArena arena;
   int top() const { return (int)lv.size() - 1; }
@@ -213,11 +234,11 @@ struct Prof {
 
 // Captured V-cycles / truncation-error cycles, replayed with hipGraphLaunch.
 struct GraphKey {
-  int kind;  // 0 isotropic V-cycle, 1 anisotropic 3V tau cycle
-  const void *Q, *S, *tau;
+  int kind;  // 0 isotropic V-cycle, 1 anisotropic 3V tau cycle, 2 FP64 isotropic V-cycle of a mixed solver
+  const void *Q, *S, *tau, *act;
   int isolated;
   bool operator<(const GraphKey& o) const {
-    return std::tie(kind, Q, S, tau, isolated) < std::tie(o.kind, o.Q, o.S, o.tau, o.isolated);
+    return std::tie(kind, Q, S, tau, act, isolated) < std::tie(o.kind, o.Q, o.S, o.tau, o.act, o.isolated);
   }
 };
 
@@ -239,7 +260,11 @@ struct pmg_solver_s {
   DevArena arena;
   Phys* d_ptab = nullptr;
   int* d_eprob = nullptr;
-  int* d_active = nullptr;                   // per problem: 0 frozen
+  int* d_ones = nullptr;                     // per problem: all 1 (every problem active, nothing skipped)
+  int* d_act[2] = {nullptr, nullptr};        // per problem: the problems a batched cycle advances
+  std::unique_ptr<Hier> iso64;               // FP64 isotropic hierarchy of a mixed-precision solver
+  std::vector<int> fp32_cycles;              // per problem: cycles of the last solve with FP32 coarse levels
+  std::vector<int> iso_caps;                 // order caps of the isotropic levels, finest first
   unsigned long long* d_red = nullptr;       // reduction slots [NSLOTS][nprob]
   double* d_zero = nullptr;                  // [5][nn] zeros (absent source)
   double* d_R = nullptr;                     // [5][nn] top-level scratch residual
@@ -292,16 +317,17 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   L.ntiles = (int)tiles.size();
   L.max_tile = max_tile;
   L.tile_target = target;
-  L.dev.tiles = L.d_tiles;
-  L.dev.elist = L.d_elist;
+  L.dev.tiles = L.dev32.tiles = L.d_tiles;
+  L.dev.elist = L.dev32.elist = L.d_elist;
 }
 
-static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int>& ord) {
+static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int>& ord, int prec = PREC_F64) {
   const pmg_mesh_s* m = s->mesh;
   auto L = std::make_shared<Level>();
   const int K = (int)m->K;
   L->K = K;
   L->fam = s->family;
+  L->prec = prec;
   L->ord = ord;
   L->off.assign(K + 1, 0);
   L->fo.assign(6 * K, 0);
@@ -397,23 +423,27 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_J = A.alloc<double>(nn);
   L->d_Nout = A.alloc<double>(3 * nf);
   L->d_mgeo = A.alloc<double>(4 * (size_t)std::max(L->nm, 1));
-  L->d_qf = A.alloc<double>(5 * nf);
-  L->d_Ws = A.alloc<double>(4 * nf);
-  L->d_gW = A.alloc<double>(12 * nn);
-  L->d_gf = A.alloc<double>(12 * nf);
-  L->d_PhiA = A.alloc<double>(5 * nf);
-  L->d_Phi = A.alloc<double>(5 * nf);
+  auto alloc_work = [&](auto& W) {
+    using T = std::remove_pointer_t<decltype(W.qf)>;
+    W.qf = A.alloc<T>(5 * nf);
+    W.Ws = A.alloc<T>(4 * nf);
+    W.gW = A.alloc<T>(12 * nn);
+    W.gf = A.alloc<T>(12 * nf);
+    W.PhiA = A.alloc<T>(5 * nf);
+    W.Phi = A.alloc<T>(5 * nf);
+  };
+  if (prec == PREC_F32) alloc_work(L->w32); else alloc_work(L->w64);
 
   LevelDev& D = L->dev;
   memset(&D, 0, sizeof(D));
   D.K = K; D.nn = (int)nn; D.nf = (int)nf; D.nm = L->nm; D.fam = L->fam;
   D.ptab = s->d_ptab; D.eprob = s->d_eprob; D.node_elem = L->d_node_elem;
   D.dt = (const double*)slot_ptr(s, SLOT_DT);
-  D.active = s->d_active;
+  D.active = s->d_ones;
   D.ord = L->d_ord; D.off = L->d_off; D.fo = L->d_fo;
   D.Ja = L->d_Ja; D.invJ = L->d_invJ; D.J = L->d_J; D.Nout = L->d_Nout;
   D.faces = L->d_faces; D.mface = L->d_mface; D.ftile = L->d_ftile; D.mgeo = L->d_mgeo;
-  D.T = s->ctx->T[L->fam];
+  D.T_ = s->ctx->T[L->fam];
   build_tiles(s, *L, 256);
 
   // geometry on the device
@@ -431,6 +461,26 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   k_geo_metric<<<nb, 256>>>(D, G);
   k_geo_faces<<<L->ntiles, PMG_BLOCK>>>(D, L->d_Nout);
   if (L->nm > 0) k_mortar_geo<<<cdiv(L->nm, 256), 256>>>(D, L->d_mgeo);
+  if (prec == PREC_F32) {
+    // FP32 copies of the metric terms, each rounded once from the FP64 geometry
+    LevelDevT<float>& F = L->dev32;
+    memset(&F, 0, sizeof(F));
+    F.K = D.K; F.nn = D.nn; F.nf = D.nf; F.nm = D.nm; F.fam = D.fam;
+    F.ptab = D.ptab; F.eprob = D.eprob; F.node_elem = D.node_elem; F.dt = D.dt; F.active = D.active;
+    F.ord = D.ord; F.off = D.off; F.fo = D.fo; F.faces = D.faces; F.mface = D.mface; F.ftile = D.ftile;
+    F.T_ = D.T_;
+    F.tiles = D.tiles; F.elist = D.elist;
+    auto down = [&](const double* src, size_t n) {
+      float* dst = A.alloc<float>(n);
+      k_copy<<<cdiv(n, 256), 256>>>(dst, src, n);
+      return (const float*)dst;
+    };
+    F.Ja = down(L->d_Ja, 9 * nn);
+    F.invJ = down(L->d_invJ, nn);
+    F.J = down(L->d_J, nn);
+    F.Nout = down(L->d_Nout, 3 * nf);
+    F.mgeo = down(L->d_mgeo, 4 * (size_t)std::max(L->nm, 1));
+  }
   HIPCHECK(hipGetLastError());
   HIPCHECK(hipDeviceSynchronize());
   return L;
@@ -473,35 +523,41 @@ static std::unique_ptr<XferTiles> build_xfer(const pmg_solver_s* s, const Level&
 // ------------------------------------------------------------------------------------------------
 // Operator, smoother, transfers
 // ------------------------------------------------------------------------------------------------
-static DivArgs div_args(int mode) {
-  DivArgs a;
+template <class T>
+static DivArgs<T> div_args(int mode) {
+  DivArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.mode = mode;
   return a;
 }
 
 // A(Q) through the stages: q traces, interface state + Roe flux, gradient (+ gradient traces), viscous
-// numerical flux, divergence (the epilogue in 'a' decides what is written).
-static void op_eval(const pmg_solver_s* s, Level& L, const double* Q, bool isolated, const DivArgs& a,
-                    hipStream_t st) {
-  const LevelDev& D = L.dev;
-  const double nn = L.nn, nf = L.nf, nm = L.nm, w = sizeof(double);
+// numerical flux, divergence (the epilogue in 'a' decides what is written).  T is the level's precision.
+// 'act' (nullable): the problems advanced by a cycle; tiles of the others return at once and leave their
+// outputs untouched (a frozen problem's state and correction stay exactly as they are).
+template <class T>
+static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, const DivArgs<T>& a,
+                    hipStream_t st, const int* act = nullptr) {
+  LevelDevT<T> D = L.devT<T>();
+  if (act) D.active = D.skip = act;
+  const Work<T>& W = L.work<T>();
+  const double nn = L.nn, nf = L.nf, nm = L.nm, w = sizeof(T);
   PROF_LAUNCH(s, PK_TRACE, st, (5 * nn + 5 * nf) * w,
-              k_trace<<<L.ntiles, PMG_BLOCK, L.lds_trace(), st>>>(D, Q, L.d_qf));
+              k_trace<T><<<L.ntiles, PMG_BLOCK, L.lds_trace(), st>>>(D, Q, W.qf));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 3 * nf + 4 * nf + 5 * nf) * w,
-                k_face1_iso<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, L.d_qf, L.d_Ws, L.d_Phi));
+                k_face1_iso<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, W.qf, W.Ws, W.Phi));
   else
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nm + 4 * nf + 5 * nf) * w,
-                k_face1<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, L.d_qf, L.d_Ws, L.d_PhiA));
+                k_face1<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.Ws, W.PhiA));
   PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn + 12 * nf) * w,
-              k_grad<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, Q, L.d_Ws, L.d_gW, L.d_gf));
+              k_grad<T><<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, Q, W.Ws, W.gW, W.gf));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 2 * 4 * nf) * w,
-                k_face2_iso<<<L.ntiles, PMG_BLOCK, 0, st>>>(D, L.d_qf, L.d_gf, L.d_Phi));
+                k_face2_iso<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, W.qf, W.gf, W.Phi));
   else
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 4 * nm + 5 * nf + 5 * nf) * w,
-                k_face2<<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, L.d_qf, L.d_gf, L.d_PhiA, L.d_Phi));
+                k_face2<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.gf, W.PhiA, W.Phi));
   // divergence: Q, grad W, J a, 1/J, Phi in; the epilogue's own arrays
   double epi = 0.0;
   switch (a.mode) {
@@ -512,7 +568,7 @@ static void op_eval(const pmg_solver_s* s, Level& L, const double* Q, bool isola
     default: epi = 5 * nn;
   }
   PROF_LAUNCH(s, PK_DIV, st, (27 * nn + 5 * nf + epi) * w,
-              k_div<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(D, Q, L.d_gW, L.d_Phi, a));
+              k_div<T><<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(D, Q, W.gW, W.Phi, a));
 }
 
 static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
@@ -542,63 +598,112 @@ static double read_slot(const pmg_solver_s* s, int slot, hipStream_t st) {
   return m;
 }
 
-static void timestep(const pmg_solver_s* s, Level& L, const double* Q, hipStream_t st) {
+template <class T>
+static void timestep(const pmg_solver_s* s, Level& L, const T* Q, hipStream_t st, const int* act = nullptr) {
   reset_slot(s, SLOT_DT, INFINITY, st);
-  PROF_LAUNCH(s, PK_DT, st, 15.0 * L.nn * sizeof(double),
-              k_dt<<<L.ntiles, PMG_BLOCK, 0, st>>>(L.dev, Q, slot_ptr(s, SLOT_DT)));
+  LevelDevT<T> D = L.devT<T>();
+  if (act) D.active = D.skip = act;
+  PROF_LAUNCH(s, PK_DT, st, 15.0 * L.nn * sizeof(T),
+              k_dt<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, slot_ptr(s, SLOT_DT)));
 }
 
-static void smooth(const pmg_solver_s* s, Level& L, double* Q, const double* S, double* G, int sweeps,
-                   hipStream_t st) {
+template <class T>
+static void smooth(const pmg_solver_s* s, Level& L, T* Q, const T* S, T* G, int sweeps, hipStream_t st,
+                   const int* act = nullptr) {
   for (int it = 0; it < sweeps; it++) {
-    timestep(s, L, Q, st);
+    timestep(s, L, (const T*)Q, st, act);
     for (int k = 0; k < 3; k++) {
-      DivArgs a = div_args(EPI_RK);
+      DivArgs<T> a = div_args<T>(EPI_RK);
       a.S = S;
       a.Qrk = Q;
       a.G = G;
       a.a = RK_A[k];
       a.b = RK_B[k];
-      op_eval(s, L, Q, false, a, st);
+      op_eval(s, L, (const T*)Q, false, a, st, act);
     }
   }
 }
 
 // out = S - A(Q); optional per-problem max-norm into a slot
-static void residual(const pmg_solver_s* s, Level& L, const double* Q, const double* S, double* out, bool isolated,
-                     int norm_slot, hipStream_t st) {
-  DivArgs a = div_args(EPI_R);
+template <class T>
+static void residual(const pmg_solver_s* s, Level& L, const T* Q, const T* S, T* out, bool isolated, int norm_slot,
+                     hipStream_t st, const int* act = nullptr) {
+  DivArgs<T> a = div_args<T>(EPI_R);
   a.S = S;
   a.out = out;
   if (norm_slot >= 0) {
     reset_slot(s, norm_slot, 0.0, st);
     a.norm = slot_ptr(s, norm_slot);
   }
-  op_eval(s, L, Q, isolated, a, st);
+  op_eval(s, L, Q, isolated, a, st, act);
 }
 
-static void xfer(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
-                 const double* U, const double* U0, double* V, bool accumulate, hipStream_t st) {
-  XferArgs a;
+// The same on buffers held in the level's own precision.
+static void smooth_any(const pmg_solver_s* s, Level& L, void* Q, const void* S, void* G, int sweeps, hipStream_t st,
+                       const int* act = nullptr) {
+  if (L.prec == PREC_F32) smooth(s, L, (float*)Q, (const float*)S, (float*)G, sweeps, st, act);
+  else smooth(s, L, (double*)Q, (const double*)S, (double*)G, sweeps, st, act);
+}
+
+static void residual_any(const pmg_solver_s* s, Level& L, const void* Q, const void* S, void* out, bool isolated,
+                         int norm_slot, hipStream_t st, const int* act = nullptr) {
+  if (L.prec == PREC_F32)
+    residual(s, L, (const float*)Q, (const float*)S, (float*)out, isolated, norm_slot, st, act);
+  else
+    residual(s, L, (const double*)Q, (const double*)S, (double*)out, isolated, norm_slot, st, act);
+}
+
+template <class TU, class TV>
+static void xfer_t(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
+                   const TU* U, const TU* U0, TV* V, bool accumulate, hipStream_t st) {
+  XferArgs<TU, TV> a;
   a.tiles = prolong ? X.d_prolong : X.d_restrict;
   a.elist = X.d_elist;
   a.off_from = from.d_off;
   a.off_to = to.d_off;
   a.nn_from = from.nn;
   a.nn_to = to.nn;
-  a.T = from.dev.T;
+  a.T = from.dev.T_;
   a.U = U;
   a.U0 = U0;
   a.V = V;
   a.accumulate = accumulate ? 1 : 0;
   a.lds_stride = X.lds_stride;
   PROF_LAUNCH(s, PK_XFER, st,
-              (5.0 * from.nn * (U0 ? 2 : 1) + 5.0 * to.nn * (accumulate ? 2 : 1)) * sizeof(double),
-              k_transfer<<<X.ntiles, PMG_BLOCK, (size_t)10 * X.lds_stride * sizeof(double), st>>>(a));
+              5.0 * from.nn * (U0 ? 2 : 1) * sizeof(TU) + 5.0 * to.nn * (accumulate ? 2 : 1) * sizeof(TV),
+              k_transfer<TU, TV><<<X.ntiles, PMG_BLOCK, (size_t)10 * X.lds_stride * sizeof(double), st>>>(a));
 }
 
-static void copy(double* dst, const double* src, size_t n, hipStream_t st) {
+// Transfer between two levels; 'U', 'U0' in the precision of 'from', 'V' in that of 'to'.
+static void xfer(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
+                 const void* U, const void* U0, void* V, bool accumulate, hipStream_t st) {
+  const bool f32 = from.prec == PREC_F32, t32 = to.prec == PREC_F32;
+  if (f32 && t32)
+    xfer_t(s, from, to, X, prolong, (const float*)U, (const float*)U0, (float*)V, accumulate, st);
+  else if (f32)
+    xfer_t(s, from, to, X, prolong, (const float*)U, (const float*)U0, (double*)V, accumulate, st);
+  else if (t32)
+    xfer_t(s, from, to, X, prolong, (const double*)U, (const double*)U0, (float*)V, accumulate, st);
+  else
+    xfer_t(s, from, to, X, prolong, (const double*)U, (const double*)U0, (double*)V, accumulate, st);
+}
+
+// Transfer of caller-owned FP64 fields, whatever the levels' working precision.
+static void xfer64(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
+                   const double* U, double* V, hipStream_t st) {
+  xfer_t(s, from, to, X, prolong, U, (const double*)nullptr, V, false, st);
+}
+
+template <class TD, class TS>
+static void copy(TD* dst, const TS* src, size_t n, hipStream_t st) {
   k_copy<<<cdiv(n, 256), 256, 0, st>>>(dst, src, n);
+}
+
+// copy of 5 x nn values held in a level's precision
+static void copy_level(const Level& L, void* dst, const void* src, hipStream_t st) {
+  size_t n = 5 * (size_t)L.nn;
+  if (L.prec == PREC_F32) copy((float*)dst, (const float*)src, n, st);
+  else copy((double*)dst, (const double*)src, n, st);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -608,7 +713,7 @@ static std::string level_key(const pmg_solver_s* s, const Level& L) {
   // structure = histogram of (order triple) buckets; the tile choice depends only on it
   std::map<int, int> h;
   for (int e = 0; e < L.K; e++) h[pack3(L.ord[3 * e], L.ord[3 * e + 1], L.ord[3 * e + 2])]++;
-  std::string k = std::to_string(L.fam) + ":" + std::to_string(s->nprob);
+  std::string k = std::to_string(L.fam) + ":" + std::to_string(L.prec) + ":" + std::to_string(s->nprob);
   for (auto& kv : h) k += "," + std::to_string(kv.first) + "x" + std::to_string(kv.second);
   return k;
 }
@@ -621,9 +726,10 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
     return;
   }
   DevArena tmp;
-  double* Q = tmp.alloc<double>(5 * (size_t)L.nn);
-  double* R = tmp.alloc<double>(5 * (size_t)L.nn);
-  k_freestream<<<cdiv(L.nn, 256), 256, 0, st>>>(L.dev, Q);
+  void* Q = tmp.alloc<char>(5 * (size_t)L.nn * L.wsize());
+  void* R = tmp.alloc<char>(5 * (size_t)L.nn * L.wsize());
+  if (L.prec == PREC_F32) k_freestream<<<cdiv(L.nn, 256), 256, 0, st>>>(L.dev32, (float*)Q);
+  else k_freestream<<<cdiv(L.nn, 256), 256, 0, st>>>(L.dev, (double*)Q);
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
@@ -633,9 +739,9 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
   float best_t = 1e30f;
   for (int target : {64, 128, 256, 512}) {
     build_tiles(s, L, target);
-    residual(s, L, Q, nullptr, R, false, -1, st);  // warm
+    residual_any(s, L, Q, nullptr, R, false, -1, st);  // warm
     HIPCHECK(hipEventRecord(e0, st));
-    for (int r = 0; r < 3; r++) residual(s, L, Q, nullptr, R, false, -1, st);
+    for (int r = 0; r < 3; r++) residual_any(s, L, Q, nullptr, R, false, -1, st);
     HIPCHECK(hipEventRecord(e1, st));
     HIPCHECK(hipEventSynchronize(e1));
     float t = 0.f;
@@ -655,7 +761,9 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
 // ------------------------------------------------------------------------------------------------
 // Hierarchies and the FAS V-cycle (Sec. 3.1, Algorithm "FAS: V-Cycle"; Sec. 3.2.3 anisotropic cycle)
 // ------------------------------------------------------------------------------------------------
-static void build_hier(pmg_solver_s* s, Hier& H, int dir, const std::vector<int>& caps_finest_first) {
+// Levels below the top run in 'coarse_prec' (FP32 in the mixed-precision cycle); the top level is FP64.
+static void build_hier(pmg_solver_s* s, Hier& H, int dir, const std::vector<int>& caps_finest_first,
+                       int coarse_prec = PREC_F64) {
   H.dir = dir;
   const int nlev = (int)caps_finest_first.size();
   const int K = (int)s->mesh->K;
@@ -674,19 +782,19 @@ static void build_hier(pmg_solver_s* s, Hier& H, int dir, const std::vector<int>
         int p = s->orders[3 * e + d];
         o[3 * e + d] = ((dir < 0 || dir == d) && p > cap) ? cap : p;
       }
-    H.lv[l] = build_level(s, o);
+    H.lv[l] = build_level(s, o, coarse_prec);
   }
   H.Q.assign(nlev, nullptr); H.Q0.assign(nlev, nullptr); H.S.assign(nlev, nullptr); H.r.assign(nlev, nullptr);
   H.Sp.assign(nlev, nullptr); H.G.assign(nlev, nullptr); H.R.assign(nlev, nullptr);
   for (int l = 0; l < nlev; l++) {
-    size_t n = 5 * (size_t)H.lv[l]->nn;
-    if (l < nlev - 1) H.Q[l] = H.arena.alloc<double>(n);  // the top state is the caller's buffer
-    H.Q0[l] = H.arena.alloc<double>(n);
-    H.S[l] = H.arena.alloc<double>(n);
-    H.r[l] = H.arena.alloc<double>(n);
-    H.Sp[l] = H.arena.alloc<double>(n);
-    H.G[l] = H.arena.alloc<double>(n);
-    H.R[l] = H.arena.alloc<double>(n);
+    size_t n = 5 * (size_t)H.lv[l]->nn * H.lv[l]->wsize();
+    if (l < nlev - 1) H.Q[l] = H.arena.alloc<char>(n);  // the top state is the caller's buffer
+    H.Q0[l] = H.arena.alloc<char>(n);
+    H.S[l] = H.arena.alloc<char>(n);
+    H.r[l] = H.arena.alloc<char>(n);
+    H.Sp[l] = H.arena.alloc<char>(n);
+    H.G[l] = H.arena.alloc<char>(n);
+    H.R[l] = H.arena.alloc<char>(n);
   }
   H.xf.clear();
   for (int l = 0; l + 1 < nlev; l++) H.xf.push_back(build_xfer(s, *H.lv[l + 1], *H.lv[l]));
@@ -703,16 +811,21 @@ struct CycleCtx {
   Hier* H;
   hipStream_t st;
   const TauRec* tau;
+  const int* act;  // nullable: the problems this cycle advances (batched solves)
 };
 
-static void restrict_to(CycleCtx& c, int l, const double* Uf, double* Uc) {
+static void restrict_to(CycleCtx& c, int l, const void* Uf, void* Uc) {
   Hier& H = *c.H;
   xfer(c.s, *H.lv[l], *H.lv[l - 1], *H.xf[l - 1], false, Uf, nullptr, Uc, false, c.st);
 }
 
-static void absmax(CycleCtx& c, const double* U, size_t n, int slot) {
+static void absmax(CycleCtx& c, const Level& L, const void* U, int slot) {
+  size_t n = 5 * (size_t)L.nn;
   reset_slot(c.s, slot, 0.0, c.st);
-  k_absmax<<<std::min(cdiv(n, 256), 2048), 256, 0, c.st>>>(U, n, slot_ptr(c.s, slot));
+  if (L.prec == PREC_F32)
+    k_absmax<<<std::min(cdiv(n, 256), 2048), 256, 0, c.st>>>((const float*)U, n, slot_ptr(c.s, slot));
+  else
+    k_absmax<<<std::min(cdiv(n, 256), 2048), 256, 0, c.st>>>((const double*)U, n, slot_ptr(c.s, slot));
 }
 
 // pre-smoothing; leaves R[l] = S - A(Q) and returns ||R||_inf when tuning (else 0)
@@ -722,20 +835,20 @@ static double pre_smooth(CycleCtx& c, int l, int top) {
   Level& L = *H.lv[l];
   const pmg_mg_params& P = s->mg;
   if (l == 0) {
-    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_coarse, c.st);
+    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_coarse, c.st, c.act);
     return 0.0;
   }
   if (!P.tuning) {
-    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_pre, c.st);
-    residual(s, L, H.Q[l], H.S[l], H.R[l], false, -1, c.st);
+    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_pre, c.st, c.act);
+    residual_any(s, L, H.Q[l], H.S[l], H.R[l], false, -1, c.st, c.act);
     return 0.0;
   }
   double rf = 0.0;
   for (int rep = 0; rep < std::max(1, P.max_repeats); rep++) {
-    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_pre, c.st);
-    residual(s, L, H.Q[l], H.S[l], H.R[l], false, SLOT_NORM, c.st);
+    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_pre, c.st, c.act);
+    residual_any(s, L, H.Q[l], H.S[l], H.R[l], false, SLOT_NORM, c.st, c.act);
     restrict_to(c, l, H.R[l], H.r[l - 1]);
-    absmax(c, H.r[l - 1], 5 * (size_t)H.lv[l - 1]->nn, SLOT_NORM2);
+    absmax(c, *H.lv[l - 1], H.r[l - 1], SLOT_NORM2);
     rf = read_slot(s, SLOT_NORM, c.st);
     double rc = read_slot(s, SLOT_NORM2, c.st);
     if (rf != rf) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual during pre-smoothing");
@@ -750,15 +863,47 @@ static void post_smooth(CycleCtx& c, int l, double rpre) {
   Level& L = *H.lv[l];
   const pmg_mg_params& P = s->mg;
   if (!P.tuning) {
-    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_post, c.st);
+    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_post, c.st, c.act);
     return;
   }
   for (int rep = 0; rep < std::max(1, P.max_repeats); rep++) {
-    smooth(s, L, H.Q[l], H.S[l], H.G[l], P.beta_post, c.st);
-    residual(s, L, H.Q[l], H.S[l], H.R[l], false, SLOT_NORM, c.st);
+    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_post, c.st, c.act);
+    residual_any(s, L, H.Q[l], H.S[l], H.R[l], false, SLOT_NORM, c.st, c.act);
     double r = read_slot(s, SLOT_NORM, c.st);
     if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual during post-smoothing");
     if (r <= rpre) break;
+  }
+}
+
+// coarse source S = A(Q~) + r (eq. FAScoarseSource) in the level's precision; in FP64 levels the truncation
+// error of the anisotropic cycle is taken from the same evaluation (or from an extra isolated one)
+template <class T>
+static void coarse_source(CycleCtx& c, int l) {
+  pmg_solver_s* s = c.s;
+  Hier& H = *c.H;
+  Level& L = *H.lv[l];
+  DivArgs<T> a = div_args<T>(EPI_SRC);
+  a.S = (const T*)H.r[l];
+  a.out = (T*)H.S[l];
+  const bool rec = c.tau != nullptr;
+  if (rec && !c.tau->isolated) {
+    a.Sphys = (const T*)H.Sp[l];
+    a.tau_map = c.tau->map;
+    a.tau_dir = H.dir;
+    a.tau_cap = H.caps[l];
+    a.tau_nt = c.tau->nt;
+    a.tau_top_ord = s->top->d_ord;
+  }
+  op_eval(s, L, (const T*)H.Q[l], false, a, c.st, c.act);
+  if (rec && c.tau->isolated) {
+    DivArgs<T> t = div_args<T>(EPI_TAU);
+    t.Sphys = (const T*)H.Sp[l];
+    t.tau_map = c.tau->map;
+    t.tau_dir = H.dir;
+    t.tau_cap = H.caps[l];
+    t.tau_nt = c.tau->nt;
+    t.tau_top_ord = s->top->d_ord;
+    op_eval(s, L, (const T*)H.Q[l], true, t, c.st, c.act);
   }
 }
 
@@ -766,34 +911,17 @@ static void vcycle_rec(CycleCtx& c, int l, int top) {
   pmg_solver_s* s = c.s;
   Hier& H = *c.H;
   Level& L = *H.lv[l];
-  const size_t n = 5 * (size_t)L.nn;
   if (l < top) {
-    // coarse source S = A(Q~) + r (eq. FAScoarseSource); truncation error from the same evaluation
-    DivArgs a = div_args(EPI_SRC);
-    a.S = H.r[l];
-    a.out = H.S[l];
-    const bool rec = c.tau != nullptr;
-    if (rec && !c.tau->isolated) {
-      a.Sphys = H.Sp[l];
-      a.tau_map = c.tau->map;
-      a.tau_dir = H.dir;
-      a.tau_cap = H.caps[l];
-      a.tau_nt = c.tau->nt;
-      a.tau_top_ord = s->top->d_ord;
-    }
-    op_eval(s, L, H.Q[l], false, a, c.st);
-    if (rec && c.tau->isolated) {
-      DivArgs t = div_args(EPI_TAU);
-      t.Sphys = H.Sp[l];
-      t.tau_map = c.tau->map;
-      t.tau_dir = H.dir;
-      t.tau_cap = H.caps[l];
-      t.tau_nt = c.tau->nt;
-      t.tau_top_ord = s->top->d_ord;
-      op_eval(s, L, H.Q[l], true, t, c.st);
+    if (L.prec == PREC_F32) {
+      if (c.tau) throw PmgError(PMG_ERR_INVALID_ARG, "truncation errors are recorded on FP64 levels only");
+      coarse_source<float>(c, l);
+    } else {
+      coarse_source<double>(c, l);
     }
   }
-  copy(H.Q0[l], H.Q[l], n, c.st);
+  // Q~0: the restricted state (on an FP32 level, the FP64 restriction rounded once); the correction
+  // Q~ - Q~0 is formed in the level's precision and added to the finer level in its precision
+  copy_level(L, H.Q0[l], H.Q[l], c.st);
   double rpre = pre_smooth(c, l, top);
   if (l > 0) {
     Level& Lc = *H.lv[l - 1];
@@ -811,17 +939,17 @@ static void set_sources(CycleCtx& c, const double* S) {
   Hier& H = *c.H;
   int top = H.top();
   size_t n = 5 * (size_t)H.lv[top]->nn;
-  copy(H.Sp[top], S ? S : c.s->d_zero, n, c.st);
+  copy((double*)H.Sp[top], S ? S : c.s->d_zero, n, c.st);
   for (int l = top; l > 0; l--) restrict_to(c, l, H.Sp[l], H.Sp[l - 1]);
 }
 
 static void run_vcycles(pmg_solver_s* s, Hier& H, double* Q, const double* S, int ncycles, const TauRec* tau,
-                        hipStream_t st) {
-  CycleCtx c{s, &H, st, tau};
+                        hipStream_t st, const int* act = nullptr) {
+  CycleCtx c{s, &H, st, tau, act};
   int top = H.top();
   H.Q[top] = Q;
   set_sources(c, S);
-  copy(H.S[top], H.Sp[top], 5 * (size_t)H.lv[top]->nn, st);
+  copy((double*)H.S[top], (const double*)H.Sp[top], 5 * (size_t)H.lv[top]->nn, st);
   for (int k = 0; k < ncycles; k++) vcycle_rec(c, top, top);
   H.Q[top] = nullptr;
 }
@@ -833,14 +961,26 @@ static Hier& aniso_hier(pmg_solver_s* s, int d) {
     std::vector<int> caps;
     for (int c = pmax; c >= 1; c--) caps.push_back(c);
     s->aniso[d] = std::make_unique<Hier>();
-    build_hier(s, *s->aniso[d], d, caps);
+    build_hier(s, *s->aniso[d], d, caps);  // truncation errors are FP64 quantities: FP64 levels
   }
   return *s->aniso[d];
 }
 
+// The FP64 isotropic hierarchy: the solver's own one, or for a mixed-precision solver a second one with
+// FP64 coarse levels, built on first use (outside any graph capture).
+static Hier& iso_f64(pmg_solver_s* s) {
+  if (s->mg.precision != 1) return s->iso;
+  if (!s->iso64) {
+    auto H = std::make_unique<Hier>();
+    build_hier(s, *H, -1, s->iso_caps, PREC_F64);
+    s->iso64 = std::move(H);
+  }
+  return *s->iso64;
+}
+
 static void tau_cycles(pmg_solver_s* s, double* Q, const double* S, const TauRec& tau, hipStream_t st) {
   size_t n = (size_t)s->mesh->K * 3 * tau.nt;
-  k_fill<<<cdiv(n, 256), 256, 0, st>>>(tau.map, n, NAN);
+  k_fill<<<cdiv(n, 256), 256, 0, st>>>(tau.map, n, (double)NAN);
   for (int d = 0; d < 3; d++) {
     Hier& H = aniso_hier(s, d);
     if (H.lv.size() < 2) continue;
@@ -1005,7 +1145,9 @@ static pmg_solver_s* create_solver(pmg_ctx ctx, const std::vector<const pmg_mesh
   REQUIRE(!(n > 1 && s->mg.tuning), "residual-based smoothing tuning is per problem: not available in a batch");
   s->d_ptab = s->arena.upload(s->phys);
   s->d_eprob = s->arena.upload(s->eprob);
-  s->d_active = s->arena.upload(std::vector<int>(n, 1));
+  s->d_ones = s->arena.upload(std::vector<int>(n, 1));
+  s->d_act[0] = s->arena.upload(std::vector<int>(n, 1));
+  s->d_act[1] = s->arena.upload(std::vector<int>(n, 1));
   s->d_red = s->arena.alloc<unsigned long long>((size_t)NSLOTS * n);
   s->top = build_level(s.get(), s->orders);
   std::vector<int> caps;
@@ -1016,8 +1158,12 @@ static pmg_solver_s* create_solver(pmg_ctx ctx, const std::vector<const pmg_mesh
     int nl = (mg && mg->n_levels > 0) ? mg->n_levels : s->nmax;
     for (int c = s->nmax; c >= 1 && (int)caps.size() < nl; c--) caps.push_back(c);
   }
+  REQUIRE(s->mg.precision == 0 || s->mg.precision == 1, "precision must be 0 (FP64) or 1 (mixed)");
+  REQUIRE(s->mg.mixed_patience >= 0, "negative mixed_patience");
   s->mg.level_caps = nullptr;
-  build_hier(s.get(), s->iso, -1, caps);
+  s->iso_caps = caps;
+  s->fp32_cycles.assign(n, 0);
+  build_hier(s.get(), s->iso, -1, caps, s->mg.precision == 1 ? PREC_F32 : PREC_F64);
   size_t nq = 5 * (size_t)s->top->nn;
   s->d_zero = s->arena.alloc<double>(nq);
   s->d_R = s->arena.alloc<double>(nq);
@@ -1211,7 +1357,7 @@ pmg_status pmg_restrict(pmg_solver s, int hierarchy, int level, const double* Uf
     REQUIRE(s && Uf && Uc, "NULL argument");
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 1 && level < (int)H.lv.size(), "level out of range");
-    xfer(s, *H.lv[level], *H.lv[level - 1], *H.xf[level - 1], false, Uf, nullptr, Uc, false, (hipStream_t)stream);
+    xfer64(s, *H.lv[level], *H.lv[level - 1], *H.xf[level - 1], false, Uf, Uc, (hipStream_t)stream);
     HIPCHECK(hipGetLastError());
   });
 }
@@ -1221,7 +1367,7 @@ pmg_status pmg_prolong(pmg_solver s, int hierarchy, int level, const double* Uc,
     REQUIRE(s && Uf && Uc, "NULL argument");
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 0 && level + 1 < (int)H.lv.size(), "level out of range");
-    xfer(s, *H.lv[level], *H.lv[level + 1], *H.xf[level], true, Uc, nullptr, Uf, false, (hipStream_t)stream);
+    xfer64(s, *H.lv[level], *H.lv[level + 1], *H.xf[level], true, Uc, Uf, (hipStream_t)stream);
     HIPCHECK(hipGetLastError());
   });
 }
@@ -1246,6 +1392,7 @@ pmg_status pmg_autotune(pmg_solver s, void* stream) {
         }
     };
     tune(s->iso);
+    if (s->iso64) tune(*s->iso64);
     for (int d = 0; d < 3; d++)
       if (s->aniso[d]) tune(*s->aniso[d]);
     for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);  // tiles changed: recapture
@@ -1270,7 +1417,7 @@ pmg_status pmg_vcycle(pmg_solver s, double* Q_dev, const double* S_dev, int n_cy
     hipStream_t st = (hipStream_t)stream;
     if (s->use_graph && !s->mg.tuning && n_cycles > 0) {
       // sources once eagerly, then the captured cycle (its sources are re-derived inside; identical work)
-      GraphKey key{0, Q_dev, S_dev, nullptr, 0};
+      GraphKey key{0, Q_dev, S_dev, nullptr, nullptr, 0};
       run_graph(s, key, n_cycles, st, [&](hipStream_t cs) { run_vcycles(s, s->iso, Q_dev, S_dev, 1, nullptr, cs); });
     } else {
       run_vcycles(s, s->iso, Q_dev, S_dev, n_cycles, nullptr, st);
@@ -1284,44 +1431,85 @@ pmg_status pmg_vcycle(pmg_solver s, double* Q_dev, const double* S_dev, int n_cy
   });
 }
 
+// One batched V-cycle of hierarchy H that advances the problems flagged in 'act' (device array).
+static void cycle_once(pmg_solver_s* s, Hier& H, int kind, double* Q, const double* S, const int* act,
+                       hipStream_t st) {
+  if (s->use_graph && !s->mg.tuning) {
+    GraphKey key{kind, Q, S, nullptr, act, 0};
+    run_graph(s, key, 1, st, [&](hipStream_t cs) { run_vcycles(s, H, Q, S, 1, nullptr, cs, act); });
+  } else {
+    run_vcycles(s, H, Q, S, 1, nullptr, st, act);
+  }
+}
+
+// Stopping and precision bookkeeping of one problem: FP32 coarse levels are kept while the residual keeps
+// reaching new minima; after 'patience' cycles without one (the FP32 round-off floor of the coarse
+// correction) the problem continues with FP64 coarse levels.
+struct MixedState {
+  int f32 = 0, stall = 0;
+  double best = INFINITY;
+  void update(double r, int patience) {
+    if (!f32) return;
+    if (r < best) {
+      best = r;
+      stall = 0;
+    } else if (++stall >= patience) {
+      f32 = 0;
+    }
+  }
+};
+
 pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double tol, int max_cycles, int* cycles_out,
                      double* res_inf_out, void* stream) {
   pmg_status rc = guard([&] {
     REQUIRE(s && Q_dev && max_cycles >= 0, "bad argument");
     hipStream_t st = (hipStream_t)stream;
-    Hier& H = s->iso;
-    CycleCtx c{s, &H, st, nullptr};
-    const int top = H.top();
-    H.Q[top] = Q_dev;
+    const bool mixed = s->mg.precision == 1;
+    const int patience = s->mg.mixed_patience > 0 ? s->mg.mixed_patience : 4;
+    Hier* H = &s->iso;
+    CycleCtx c{s, H, st, nullptr, nullptr};
+    const int top = H->top();
+    H->Q[top] = Q_dev;
     set_sources(c, S_dev);
-    int cycles = 0;
+    int cycles = 0, c32 = 0;
     double r = 0.0;
     if (s->mg.fmg) {
-      for (int l = top; l > 0; l--) restrict_to(c, l, H.Q[l], H.Q[l - 1]);
+      for (int l = top; l > 0; l--) restrict_to(c, l, H->Q[l], H->Q[l - 1]);
       for (int l = 0; l < top; l++) {
-        Level& L = *H.lv[l];
-        copy(H.S[l], H.Sp[l], 5 * (size_t)L.nn, st);
+        Level& L = *H->lv[l];
+        copy_level(L, H->S[l], H->Sp[l], st);
         for (;;) {
-          residual(s, L, H.Q[l], H.Sp[l], H.R[l], false, SLOT_NORM, st);
+          residual_any(s, L, H->Q[l], H->Sp[l], H->R[l], false, SLOT_NORM, st);
           r = read_slot(s, SLOT_NORM, st);
           if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual in the FMG start");
           if (r < s->mg.fmg_threshold || cycles >= max_cycles) break;
           vcycle_rec(c, l, l);
           cycles++;
+          c32 += mixed;
         }
-        xfer(s, L, *H.lv[l + 1], *H.xf[l], true, H.Q[l], nullptr, H.Q[l + 1], false, st);
+        xfer(s, L, *H->lv[l + 1], *H->xf[l], true, H->Q[l], nullptr, H->Q[l + 1], false, st);
       }
     }
-    copy(H.S[top], H.Sp[top], 5 * (size_t)H.lv[top]->nn, st);
+    H->Q[top] = nullptr;
+    MixedState ms;
+    ms.f32 = mixed;
     for (;;) {
-      residual(s, *H.lv[top], Q_dev, H.Sp[top], s->d_R, false, SLOT_NORM, st);
+      residual(s, *s->top, (const double*)Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
       r = read_slot(s, SLOT_NORM, st);
       if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
       if (r < tol || cycles >= max_cycles) break;
-      vcycle_rec(c, top, top);
+      ms.update(r, patience);
+      if (s->mg.tuning) {
+        // residual-based tuning reads norms inside the cycle: eager launches
+        Hier& Hc = ms.f32 ? s->iso : iso_f64(s);
+        run_vcycles(s, Hc, Q_dev, S_dev, 1, nullptr, st);
+      } else {
+        cycle_once(s, ms.f32 ? s->iso : iso_f64(s), ms.f32 ? 0 : 2, Q_dev, S_dev, nullptr, st);
+      }
       cycles++;
+      c32 += ms.f32;
     }
-    H.Q[top] = nullptr;
+    s->fp32_cycles.assign(s->nprob, c32);
     if (cycles_out) *cycles_out = cycles;
     if (res_inf_out) *res_inf_out = r;
     if (r >= tol) throw PmgError(PMG_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance");
@@ -1336,43 +1524,57 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
     REQUIRE(s && Q_dev && max_cycles >= 0, "bad argument");
     hipStream_t st = (hipStream_t)stream;
     const int n = s->nprob;
-    std::vector<int> active(n, 1), cyc(n, 0);
+    const bool mixed = s->mg.precision == 1;
+    const int patience = s->mg.mixed_patience > 0 ? s->mg.mixed_patience : 4;
+    std::vector<int> active(n, 1), cyc(n, 0), c32(n, 0), a32(n, 0), a64(n, 0);
+    std::vector<MixedState> ms(n);
+    for (auto& m : ms) m.f32 = mixed;
     std::vector<double> r(n, 0.0);
-    bool done = false;
-    for (int k = 0;; k++) {
-      residual(s, *s->top, Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
+    for (;;) {
+      residual(s, *s->top, (const double*)Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);  // every problem
       r = read_slots(s, SLOT_NORM, st);
-      int nact = 0;
+      int n32 = 0, n64 = 0;
       for (int p = 0; p < n; p++) {
         if (r[p] != r[p]) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual in problem " + std::to_string(p));
         if (active[p] && (r[p] < tol || cyc[p] >= max_cycles)) active[p] = 0;  // converged problems freeze
-        nact += active[p];
+        if (active[p]) ms[p].update(r[p], patience);
+        a32[p] = active[p] && ms[p].f32;
+        a64[p] = active[p] && !ms[p].f32;
+        n32 += a32[p];
+        n64 += a64[p];
       }
-      if (nact == 0) {
-        done = true;
-        break;
+      if (n32 + n64 == 0) break;
+      // the previous iteration's reads synchronised the stream: the flag arrays are free to rewrite
+      if (n32) {
+        HIPCHECK(hipMemcpyAsync(s->d_act[0], a32.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+        cycle_once(s, s->iso, 0, Q_dev, S_dev, s->d_act[0], st);
       }
-      HIPCHECK(hipMemcpyAsync(s->d_active, active.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
-      if (s->use_graph) {
-        GraphKey key{0, Q_dev, S_dev, nullptr, 0};
-        run_graph(s, key, 1, st, [&](hipStream_t cs) { run_vcycles(s, s->iso, Q_dev, S_dev, 1, nullptr, cs); });
-      } else {
-        run_vcycles(s, s->iso, Q_dev, S_dev, 1, nullptr, st);
+      if (n64) {
+        HIPCHECK(hipMemcpyAsync(s->d_act[1], a64.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+        cycle_once(s, iso_f64(s), mixed ? 2 : 0, Q_dev, S_dev, s->d_act[1], st);
       }
-      for (int p = 0; p < n; p++) cyc[p] += active[p];
+      for (int p = 0; p < n; p++) {
+        cyc[p] += active[p];
+        c32[p] += a32[p];
+      }
     }
-    std::vector<int> ones(n, 1);
-    HIPCHECK(hipMemcpy(s->d_active, ones.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    s->fp32_cycles = c32;
     bool all = true;
     for (int p = 0; p < n; p++) {
       if (cycles_out) cycles_out[p] = cyc[p];
       if (res_inf_out) res_inf_out[p] = r[p];
       all = all && r[p] < tol;
     }
-    (void)done;
     if (!all) throw PmgError(PMG_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance in some problem");
   });
   return rc;
+}
+
+pmg_status pmg_solve_stats(pmg_solver s, int32_t* fp32_cycles) {
+  return guard([&] {
+    REQUIRE(s && fp32_cycles, "NULL argument");
+    for (int p = 0; p < s->nprob; p++) fp32_cycles[p] = s->fp32_cycles[p];
+  });
 }
 
 pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, int isolated, double* tau_map_dev,
@@ -1384,7 +1586,7 @@ pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, in
     TauRec tau{tau_map_dev, nt, isolated ? 1 : 0};
     for (int d = 0; d < 3; d++) aniso_hier(s, d);  // built before any capture
     if (s->use_graph) {
-      GraphKey key{1, Q_dev, S_dev, tau_map_dev, tau.isolated};
+      GraphKey key{1, Q_dev, S_dev, tau_map_dev, nullptr, tau.isolated};
       run_graph(s, key, 1, st, [&](hipStream_t cs) { tau_cycles(s, Q_dev, S_dev, tau, cs); });
     } else {
       tau_cycles(s, Q_dev, S_dev, tau, st);

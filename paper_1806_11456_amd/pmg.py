@@ -25,7 +25,7 @@ EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_crea
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
            "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
-           "pmg_level_tiles"]
+           "pmg_level_tiles", "pmg_solve_stats"]
 
 # kernel kinds of pmg_profile_enable / pmg_profile_read
 KINDS = {"trace": 0, "face1": 1, "grad": 2, "face2": 3, "div": 4, "dt": 5, "transfer": 6}
@@ -46,7 +46,8 @@ class Physics(C.Structure):
 class MGParams(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("level_caps", C.POINTER(C.c_int32)), ("beta_pre", C.c_int32),
                 ("beta_post", C.c_int32), ("beta_coarse", C.c_int32), ("tuning", C.c_int32), ("eta", C.c_double),
-                ("max_repeats", C.c_int32), ("fmg", C.c_int32), ("fmg_threshold", C.c_double)]
+                ("max_repeats", C.c_int32), ("fmg", C.c_int32), ("fmg_threshold", C.c_double),
+                ("precision", C.c_int32), ("mixed_patience", C.c_int32)]
 
 
 @dataclasses.dataclass
@@ -60,6 +61,8 @@ class MG:
     max_repeats: int = 10
     fmg: int = 0
     fmg_threshold: float = 0.1
+    precision: int = 0  # 0 all FP64; 1 mixed (FP32 coarse-level smoothing, FP64 finest level)
+    mixed_patience: int = 0  # mixed: cycles without a new residual minimum before FP64 coarse levels (0 = 4)
 
 
 _lib = None
@@ -188,7 +191,7 @@ class Solver:
         return MGParams(0 if caps is None else len(caps),
                         None if caps is None else caps.ctypes.data_as(C.POINTER(C.c_int32)),
                         mg.beta_pre, mg.beta_post, mg.beta_coarse, mg.tuning, mg.eta, mg.max_repeats, mg.fmg,
-                        mg.fmg_threshold)
+                        mg.fmg_threshold, mg.precision, mg.mixed_patience)
 
     def _setup(self, ctx, h, K, orders, mg):
         import torch
@@ -272,6 +275,13 @@ class Solver:
         if rc != 0 and (rc != 5 or raise_not_converged):
             _check(rc)
         return int(cyc.value), float(r.value)
+
+    def fp32_cycles(self):
+        """Per problem: cycles of the last solve that ran with FP32 coarse levels (mixed precision)."""
+        n = getattr(self, "n", 1)
+        out = np.zeros(n, dtype=np.int32)
+        _check(lib().pmg_solve_stats(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out
 
     def profile(self, kinds):
         """Bracket every launch of the given kernel kinds with HIP events (empty = off)."""

@@ -1,0 +1,127 @@
+"""Mixed precision on the GPU: FP32 coarse-level smoothing inside an FP64 defect correction.
+
+* One mixed V-cycle stays within FP32 round-off of the oracle's FP64 V-cycle (relative to the correction it
+  makes) and is not bitwise the FP64 cycle, so the FP32 levels really run.
+* A mixed solve with the precision switch reaches the FP64 tolerance: the oracle's FP64 residual of its
+  result is below the tolerance, and it agrees with the FP64 solve within 1e-9 per variable.
+* A batch of mixed solves equals the same solves run one by one, bitwise, switch points included.
+
+The manufactured problems take S = A(Q*) from the oracle for a smooth Q* on a curved box.  The converged
+comparison uses far-field boundaries: on a periodic box the DG operator conserves the domain integrals of
+Q, the steady solution is fixed only up to them, and FP32 coarse corrections move them by FP32 round-off,
+which no FP64 residual sees (the drift is measured, not bounded, in the periodic variant).
+"""
+import numpy as np
+import pytest
+
+from paper_1806_11456_amd import inputs as I
+from tests.gpu_util import check, np_
+
+pytestmark = pytest.mark.gpu
+
+MG = dict(beta_pre=2, beta_post=2, beta_coarse=4)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1806_11456_amd import pmg
+    assert torch.cuda.is_available()
+    return pmg.Context(0)
+
+
+def manufactured(hi=4, reynolds=20.0, periodic=True):
+    """Curved 3x3x3 box (periodic, or far field on every side), random orders 1..hi, smooth target Q*,
+    start Q* (1 + 1e-2 sin)."""
+    from oracle import oracle as O
+    per = (periodic,) * 3
+    base = I.box_mesh((3, 3, 3), (-1, -1, -1), (1, 1, 1), M=(2, 2, 2), wobble=0.12, periodic=per)
+    mesh, orders = I.reorient(base, 21, period=(2, 2, 2) if periodic else None,
+                              orders=I.random_orders(base.K, 1, hi, 22))
+    ph = I.Physics(mach=0.3, reynolds=reynolds, cfl_adv=0.2, cfl_visc=0.2)
+    Qt = I.box_wave_state(mesh, orders, ph.family, ph.mach, amp=0.0)
+    x, y, z = I.node_coords(mesh, orders, ph.family)
+    Q0 = Qt * (1.0 + 1e-2 * np.sin(np.pi * (x + 2 * y)))[None]
+    o = O.Oracle(mesh, ph)
+    S = o.operator(orders, Qt)
+    return mesh, orders, ph, Q0, S, o
+
+
+@pytest.fixture(scope="module")
+def problem():
+    return manufactured()
+
+
+@pytest.fixture(scope="module")
+def bounded():
+    return manufactured(periodic=False)
+
+
+def test_mixed_vcycle_tracks_fp64_oracle(ctx, problem):
+    from paper_1806_11456_amd import pmg
+    mesh, orders, ph, Q0, S, o = problem
+    m = pmg.Mesh(ctx, mesh)
+    mixed = pmg.Solver(ctx, m, orders, ph, pmg.MG(precision=1, **MG))
+    fp64 = pmg.Solver(ctx, m, orders, ph, pmg.MG(precision=0, **MG))
+    Qm, Qd = mixed.tensor(Q0), fp64.tensor(Q0)
+    mixed.vcycle(Qm, mixed.tensor(S), n_cycles=1)
+    fp64.vcycle(Qd, fp64.tensor(S), n_cycles=1)
+    Qo, _ = o.vcycles(orders, Q0, S, ncycles=1, **MG)  # default levels: max order down to 1, as the solver's
+    # the coarse levels hold the state rounded to FP32 and each RK stage there rounds again: the correction
+    # carries a few FP32 units (2^-24 max |Q_v|) of noise per stage; bound: 100 units
+    u32 = 2.0 ** -24
+    scale = np.abs(Q0).max(axis=1, keepdims=True)
+    err = check(np_(Qm) - Q0, Qo - Q0, scale, 100 * u32, "mixed V-cycle correction")
+    print(f"mixed V-cycle correction error: {err / u32:.1f} FP32 units of max |Q|")
+    assert not np.array_equal(np_(Qm), np_(Qd)), "mixed cycle is bitwise the FP64 cycle: FP32 levels not used"
+
+
+@pytest.mark.parametrize("which", ["bounded", "periodic"])
+def test_mixed_solve_reaches_fp64_solution(ctx, problem, bounded, which):
+    from paper_1806_11456_amd import pmg
+    mesh, orders, ph, Q0, S, o = bounded if which == "bounded" else problem
+    m = pmg.Mesh(ctx, mesh)
+    tol = 1e-9
+    res = {}
+    for prec in (0, 1):
+        s = pmg.Solver(ctx, m, orders, ph, pmg.MG(precision=prec, **MG))
+        s.set_graph(True)
+        Q = s.tensor(Q0)
+        cyc, r = s.solve(Q, s.tensor(S), tol=tol, max_cycles=600)
+        res[prec] = (np_(Q), cyc, int(s.fp32_cycles()[0]))
+        print(f"precision {prec}: {cyc} cycles, {res[prec][2]} with FP32 coarse levels, residual {r:.3e}")
+    Qd, cd, f32d = res[0]
+    Qm, cm, f32m = res[1]
+    assert f32d == 0
+    assert 0 < f32m < cm, "the mixed solve should start on FP32 coarse levels and switch to FP64 ones"
+    # the oracle's FP64 residual of the mixed result
+    A, scale = o.operator_scale(orders, Qm)
+    assert np.abs(S - A).max() <= tol + 1e-12 * scale.max()
+    if which == "bounded":
+        # unique steady solution: the mixed and FP64 converged solutions agree within 1e-9 per variable
+        check(Qm, Qd, None, 1e-9, "mixed vs FP64 converged solution")
+    else:
+        # periodic: the difference is the drift of the conserved integrals (reported)
+        rel = np.abs(Qm - Qd).max(axis=1) / np.abs(Qd).max(axis=1)
+        print("periodic box, mixed vs FP64 solution per variable:", rel)
+
+
+def test_mixed_batch_equals_single(ctx):
+    from paper_1806_11456_amd import pmg
+    problems = I.config_batch(n=3, kmin=20, kmax=60, seed=7)
+    mg = pmg.MG(precision=1, mixed_patience=2, **MG)
+    meshes = [pmg.Mesh(ctx, w.mesh) for w in problems]
+    b = pmg.Batch(ctx, meshes, [w.orders for w in problems], [w.phys for w in problems], mg)
+    Qb = b.tensor(np.concatenate([w.Q for w in problems], axis=1))
+    r0 = b.norms(Qb)
+    tol = float(np.min(r0)) * 1e-3
+    cyc, r = b.solve_all(Qb, None, tol=tol, max_cycles=30, raise_not_converged=False)
+    f32 = b.fp32_cycles()
+    print("batch cycles", cyc, "fp32 cycles", f32)
+    for p, (mesh, w) in enumerate(zip(meshes, problems)):
+        s = pmg.Solver(ctx, mesh, w.orders, w.phys, mg)
+        Qs = s.tensor(w.Q)
+        cs, rs = s.solve(Qs, None, tol=tol, max_cycles=30, raise_not_converged=False)
+        assert (cs, int(s.fp32_cycles()[0])) == (cyc[p], f32[p]), p
+        assert rs == r[p]
+        assert np.array_equal(np_(b.part(Qb, p)), np_(Qs)), p
