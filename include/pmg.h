@@ -57,6 +57,7 @@ typedef enum {
 typedef struct pmg_ctx_s* pmg_ctx;       /* one GPU */
 typedef struct pmg_mesh_s* pmg_mesh;     /* geometry + connectivity, copied to the GPU */
 typedef struct pmg_solver_s* pmg_solver; /* mesh + order tensor + physics + multigrid hierarchy */
+typedef struct pmg_server_s* pmg_server; /* continuous-batching solve server on one GPU */
 
 /* Physics (Appendix A; CFL constants of Sec. 2). */
 typedef struct {
@@ -213,6 +214,51 @@ pmg_status pmg_batch_norms(pmg_solver s, const double* Q_dev, const double* S_de
  * cycles per iteration, each skipping the other set.  cycles_out / res_inf_out: n entries. */
 pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, double tol, int max_cycles,
                            int32_t* cycles_out, double* res_inf_out, void* stream);
+/*
+ * Device footprint of a single-problem solver for (mesh, orders, mg) as pmg_solver_create builds it,
+ * counted on the host from the connectivity and the orders: every level's geometry, face and work arrays,
+ * the multigrid arrays of the isotropic hierarchy and the solver's own arrays; not the mesh's geometry
+ * nodes.  Built later, on first use, and reported apart: transient_bytes (nullable), the extra memory held
+ * while a level's geometry is computed during construction; switch_bytes (nullable), the FP64 coarse
+ * hierarchy a mixed-precision solver builds when it switches precision (0 with precision 0).  The
+ * anisotropic truncation-error hierarchies of pmg_tau_estimate are not counted.
+ */
+pmg_status pmg_footprint(pmg_mesh mesh, const int32_t* orders, const pmg_mg_params* mg, int64_t* bytes,
+                         int64_t* transient_bytes, int64_t* switch_bytes);
+/* Device bytes currently allocated by the library (every handle, every device). */
+pmg_status pmg_device_bytes(int64_t* bytes);
+
+/*
+ * Serving (steady solves of independent problems arriving over time).  A request is a problem (mesh,
+ * orders, physics, multigrid parameters without tuning or FMG), a caller-owned state Q_dev holding the
+ * initial state (its producing work complete when submitted; solved in place) and a stopping test
+ * (fine-level FP64 ||r||_inf < tol, at most max_cycles V-cycles, as pmg_solve).  The mesh and Q_dev must
+ * stay alive until the request is done.
+ * - Admission: requests are admitted first come, first served, when the sum of the footprints (pmg_footprint
+ *   with its construction transient and precision-switch hierarchy) of the resident requests and of the next one fits hbm_budget_bytes.
+ *   Its solver (all levels) stays resident until the request retires.  A request larger than the whole
+ *   budget is refused at submission with PMG_ERR_OOM.
+ * - Continuous batching at V-cycle granularity: a worker thread repeatedly runs one V-cycle of every
+ *   resident unfinished request, spread over n_streams HIP streams (captured graphs when use_graph = 1),
+ *   then every request's residual norm, then waits once; new arrivals join at the next iteration, converged
+ *   or failed requests retire and release their memory.
+ * - Each request runs exactly the launch sequence of pmg_solve on its own solver (mixed-precision switch
+ *   included), so its result is bitwise the result of solving it alone.
+ * The server's functions may be called from any thread.  Destroying the server stops the worker after its
+ * current iteration; requests still resident or queued are abandoned (their state is left as it is).
+ */
+pmg_status pmg_server_create(pmg_ctx ctx, int64_t hbm_budget_bytes, int n_streams, int use_graph, pmg_server* out);
+pmg_status pmg_server_submit(pmg_server sv, pmg_mesh mesh, const int32_t* orders, const pmg_physics* phys,
+                             const pmg_mg_params* mg, double* Q_dev, double tol, int max_cycles, uint64_t* ticket);
+/* done = 0 while queued or resident.  When done: status (PMG_OK converged, PMG_ERR_NOT_CONVERGED,
+ * PMG_ERR_NONPHYSICAL, ...), cycles run, of which fp32_cycles on FP32 coarse levels, the final residual,
+ * latency = submission to retirement and queue_s = submission to admission, in seconds (all nullable). */
+pmg_status pmg_server_poll(pmg_server sv, uint64_t ticket, int* done, int* status, int* cycles, int* fp32_cycles,
+                           double* res_inf, double* latency_s, double* queue_s);
+pmg_status pmg_server_stats(pmg_server sv, int* resident, int* queued, int64_t* completed, int64_t* iterations,
+                            int64_t* bytes_in_use, int64_t* peak_bytes, int* max_resident);
+void pmg_server_destroy(pmg_server sv);
+
 /* Mixed precision (pmg_mg_params.precision = 1, Sec. 3.1 cycle with FP32 coarse levels): fp32_cycles (host,
  * one entry per problem) receives the number of cycles of the last pmg_solve / pmg_batch_solve that ran
  * with FP32 coarse levels before the switch to FP64 ones (0 for an FP64 solver). */

@@ -3,6 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -66,14 +72,20 @@ pmg_status guard(F&& f) {
 inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 
 // device allocations owned by a level / solver
+// Bytes the library has requested from hipMalloc and not yet freed (all handles, all devices).
+std::atomic<long long> g_dev_bytes{0};
+
 struct DevArena {
   std::vector<void*> ptrs;
+  long long bytes = 0;
   template <class T>
   T* alloc(size_t n) {
     if (n == 0) n = 1;
     void* p = nullptr;
     HIPCHECK(hipMalloc(&p, n * sizeof(T)));
     ptrs.push_back(p);
+    bytes += (long long)(n * sizeof(T));
+    g_dev_bytes += (long long)(n * sizeof(T));
     return (T*)p;
   }
   template <class T>
@@ -84,6 +96,7 @@ struct DevArena {
   }
   ~DevArena() {
     for (void* p : ptrs) (void)hipFree(p);
+    g_dev_bytes -= bytes;
   }
 };
 
@@ -550,8 +563,10 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
   else
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nm + 4 * nf + 5 * nf) * w,
                 k_face1<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.Ws, W.PhiA));
+  const bool one = L.max_tile <= PMG_BLOCK;  // one node per thread in every tile
   PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn + 12 * nf) * w,
-              k_grad<T><<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(D, Q, W.Ws, W.gW, W.gf));
+              (one ? k_grad<T, 1> : k_grad<T, PMG_NPT>)<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(
+                  D, Q, W.Ws, W.gW, W.gf));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 2 * 4 * nf) * w,
                 k_face2_iso<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, W.qf, W.gf, W.Phi));
@@ -568,7 +583,8 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
     default: epi = 5 * nn;
   }
   PROF_LAUNCH(s, PK_DIV, st, (27 * nn + 5 * nf + epi) * w,
-              k_div<T><<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(D, Q, W.gW, W.Phi, a));
+              (one ? k_div<T, 1> : k_div<T, PMG_NPT>)<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(
+                  D, Q, W.gW, W.Phi, a));
 }
 
 static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
@@ -1176,6 +1192,97 @@ static pmg_solver_s* create_solver(pmg_ctx ctx, const std::vector<const pmg_mesh
 }
 
 // ------------------------------------------------------------------------------------------------
+// Device footprint of a solver, counted on the host from the connectivity and the orders (the same
+// allocations as the level, hierarchy and solver construction above; the anisotropic truncation-error
+// hierarchies are built on first use and are not included).
+// ------------------------------------------------------------------------------------------------
+struct LevelCount {
+  double nn = 0, nf = 0, nm = 0, nfaces = 0, ntiles = 0;
+};
+
+static LevelCount count_level(const pmg_mesh_s* m, const std::vector<int>& ord, const std::vector<int>& eprob) {
+  LevelCount c;
+  const int64_t K = m->K;
+  std::map<std::pair<int, int>, int> buckets;
+  for (int64_t e = 0; e < K; e++) {
+    int n1 = ord[3 * e] + 1, n2 = ord[3 * e + 1] + 1, n3 = ord[3 * e + 2] + 1;
+    c.nn += (double)n1 * n2 * n3;
+    c.nf += 2.0 * (n2 * n3 + n1 * n3 + n1 * n2);
+    buckets[{eprob[e], pack3(n1, n2, n3)}]++;
+    for (int f = 0; f < 6; f++) {
+      int64_t g = m->nbr[6 * e + f];
+      int h = m->nbrf[6 * e + f];
+      if (!(g < 0 || e < g || (e == g && f < h))) continue;
+      int d = f / 2, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      int ms = ord[3 * e + t1] + 1, mt = ord[3 * e + t2] + 1;
+      if (g >= 0) {
+        int o = m->orient[6 * e + f], dg = h / 2, s1 = dg == 0 ? 1 : 0, s2 = dg == 2 ? 1 : 2;
+        int nS1 = ord[3 * g + s1] + 1, nS2 = ord[3 * g + s2] + 1;
+        ms = std::max(ms, (o & 4) ? nS2 : nS1);
+        mt = std::max(mt, (o & 4) ? nS1 : nS2);
+      }
+      c.nm += (double)ms * mt;
+      c.nfaces += 1;
+    }
+  }
+  for (auto& kv : buckets) {
+    int key = kv.first.second, npe = (key & 255) * ((key >> 8) & 255) * (key >> 16);
+    int per = std::max(1, std::min(PMG_MAX_TILE_ELEMS, 256 / npe));
+    while (per > 1 && per * npe > PMG_TILE_MAX) per--;
+    c.ntiles += (kv.second + per - 1) / per;
+  }
+  return c;
+}
+
+// Bytes of one level (arena + element tiles) and of its hierarchy arrays ('top': the state is the caller's).
+static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
+  const double w = prec == PREC_F32 ? 4.0 : 8.0;
+  double b = 4.0 * (3 * K + (K + 1) + 6 * K + c.nn + c.nm + c.nm / 64.0 + 2) + sizeof(FaceRec) * c.nfaces;
+  b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));  // FP64 geometry
+  b += w * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf + 5 * c.nf);  // work arrays
+  if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
+  b += 4.0 * K + 16.0 * c.ntiles;                  // element tiles
+  b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
+  b += 4.0 * K + 2 * 16.0 * K;                     // transfer tiles towards this level (upper bound)
+  return b;
+}
+
+// Footprint of one problem's solver as constructed; 'transient' receives the extra bytes held while a
+// level's geometry is being built, 'switch_extra' the FP64 coarse hierarchy a mixed-precision solver builds
+// when it switches precision.
+static double solver_footprint(const pmg_mesh_s* m, const int32_t* orders, const pmg_mg_params* mg,
+                               double* transient, double* switch_extra) {
+  const int64_t K = m->K;
+  std::vector<int> ord(orders, orders + 3 * K), eprob(K, 0);
+  int pmax = 1;
+  for (int v : ord) pmax = std::max(pmax, v);
+  std::vector<int> caps;
+  if (mg && mg->n_levels > 0 && mg->level_caps) caps.assign(mg->level_caps, mg->level_caps + mg->n_levels);
+  else
+    for (int c = pmax; c >= 1 && (int)caps.size() < ((mg && mg->n_levels > 0) ? mg->n_levels : pmax); c--)
+      caps.push_back(c);
+  const bool mixed = mg && mg->precision == 1;
+  double b = 0.0, nn_top = 0.0, extra = 0.0;
+  for (size_t l = 0; l < caps.size(); l++) {
+    std::vector<int> o(ord);
+    if (l > 0)
+      for (auto& v : o) v = std::min(v, caps[l]);
+    LevelCount c = count_level(m, o, eprob);
+    if (l == 0) {
+      nn_top = c.nn;
+      b += level_bytes(c, K, PREC_F64, true);
+    } else {
+      b += level_bytes(c, K, mixed ? PREC_F32 : PREC_F64, false);
+      if (mixed) extra += level_bytes(c, K, PREC_F64, false);  // the FP64 hierarchy of the precision switch
+    }
+  }
+  b += sizeof(Phys) + 4.0 * K + 3 * 4.0 + 8.0 * NSLOTS + 3 * 5 * 8.0 * nn_top;  // solver arrays
+  if (transient) *transient = 12.0 * 8.0 * nn_top;
+  if (switch_extra) *switch_extra = extra;
+  return b;
+}
+
+// ------------------------------------------------------------------------------------------------
 // C ABI
 // ------------------------------------------------------------------------------------------------
 extern "C" {
@@ -1575,6 +1682,292 @@ pmg_status pmg_solve_stats(pmg_solver s, int32_t* fp32_cycles) {
     REQUIRE(s && fp32_cycles, "NULL argument");
     for (int p = 0; p < s->nprob; p++) fp32_cycles[p] = s->fp32_cycles[p];
   });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// Serving: continuous batching of steady solves at V-cycle granularity
+// ------------------------------------------------------------------------------------------------
+// Each admitted request owns a solver (its levels stay resident until it retires) and runs on one of the
+// server's streams.  One worker thread loops: admit queued requests whose footprint fits the budget,
+// launch one V-cycle of every resident request that is not done, launch every resident request's residual
+// norm with its copy to pinned host memory, wait for the streams once, then retire converged (or failed)
+// requests and free their memory.  Every request sees the launch sequence of pmg_solve (residual, test,
+// cycle), so its result does not depend on what else is resident.
+struct ServerReq {
+  uint64_t ticket = 0;
+  const pmg_mesh_s* mesh = nullptr;
+  std::vector<int32_t> orders;
+  pmg_physics phys;
+  pmg_mg_params mg;
+  std::vector<int32_t> caps;
+  double tol = 0.0;
+  int max_cycles = 0;
+  double* Q = nullptr;
+  double est = 0.0;  // admitted bytes (steady footprint + construction transient)
+  double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+  pmg_solver_s* s = nullptr;
+  hipStream_t st = nullptr;
+  double* h_norm = nullptr;  // pinned
+  int cycles = 0, fp32 = 0, status = -1, done = 0;
+  bool cycle_next = false;
+  MixedState ms;
+  double r = 0.0;
+  std::string err;
+};
+
+struct pmg_server_s {
+  pmg_ctx ctx = nullptr;
+  double budget = 0.0;
+  int graph = 1;
+  std::vector<hipStream_t> streams;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::shared_ptr<ServerReq>> queue;
+  std::vector<std::shared_ptr<ServerReq>> resident;
+  std::map<uint64_t, std::shared_ptr<ServerReq>> all;
+  double used = 0.0, peak = 0.0;
+  uint64_t next_ticket = 1;
+  int64_t completed = 0, iterations = 0;
+  int max_resident = 0;
+  bool stop = false;
+  std::string fatal;
+  std::thread worker;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+static void server_retire(pmg_server_s* sv, const std::shared_ptr<ServerReq>& r, int status) {
+  delete r->s;
+  r->s = nullptr;
+  if (r->h_norm) (void)hipHostFree(r->h_norm);
+  r->h_norm = nullptr;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  r->status = status;
+  r->t_done = sv->now();
+  r->done = 1;
+  sv->used -= r->est;
+  sv->completed++;
+}
+
+static void server_loop(pmg_server_s* sv) {
+  if (hipSetDevice(sv->ctx->device) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->fatal = "hipSetDevice failed in the server thread";
+    return;
+  }
+  size_t rr = 0;
+  for (;;) {
+    std::vector<std::shared_ptr<ServerReq>> admit;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      if (sv->resident.empty()) sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+      if (sv->stop) break;
+      // first come, first served: a request waits until everything submitted before it is admitted
+      while (!sv->queue.empty() && sv->used + sv->queue.front()->est <= sv->budget) {
+        auto r = sv->queue.front();
+        sv->queue.pop_front();
+        sv->used += r->est;
+        sv->peak = std::max(sv->peak, sv->used);
+        r->t_admit = sv->now();
+        admit.push_back(r);
+      }
+    }
+    for (auto& r : admit) {
+      pmg_status rc = guard([&] {
+        r->mg.level_caps = r->caps.empty() ? nullptr : r->caps.data();
+        r->s = create_solver(sv->ctx, {r->mesh}, {r->orders.data()}, &r->phys, &r->mg);
+        r->s->use_graph = sv->graph;
+        r->st = sv->streams[rr++ % sv->streams.size()];
+        HIPCHECK(hipHostMalloc((void**)&r->h_norm, sizeof(double), hipHostMallocDefault));
+        r->ms.f32 = r->s->mg.precision == 1;
+      });
+      if (rc != PMG_OK) {
+        r->err = g_err;
+        server_retire(sv, r, rc);
+        continue;
+      }
+      sv->resident.push_back(r);
+      sv->max_resident = std::max(sv->max_resident, (int)sv->resident.size());
+    }
+    if (sv->resident.empty()) continue;
+    // one iteration: the decided cycle, then the residual norm, for every resident request
+    for (auto& r : sv->resident) {
+      pmg_status rc = guard([&] {
+        pmg_solver_s* s = r->s;
+        if (r->cycle_next) {
+          cycle_once(s, r->ms.f32 ? s->iso : iso_f64(s), r->ms.f32 ? 0 : 2, r->Q, nullptr, nullptr, r->st);
+          r->cycles++;
+          r->fp32 += r->ms.f32;
+        }
+        residual(s, *s->top, (const double*)r->Q, (const double*)nullptr, s->d_R, false, SLOT_NORM, r->st);
+        HIPCHECK(hipMemcpyAsync(r->h_norm, slot_ptr(s, SLOT_NORM), sizeof(double), hipMemcpyDeviceToHost, r->st));
+      });
+      if (rc != PMG_OK) {
+        r->err = g_err;
+        r->status = rc;
+      }
+    }
+    for (hipStream_t st : sv->streams) (void)hipStreamSynchronize(st);
+    sv->iterations++;
+    std::vector<std::shared_ptr<ServerReq>> keep;
+    for (auto& r : sv->resident) {
+      int status = r->status >= 0 ? r->status : -1;
+      if (status < 0) {
+        r->r = *r->h_norm;
+        if (r->r != r->r) {
+          r->err = "non-finite residual";
+          status = PMG_ERR_NONPHYSICAL;
+        } else if (r->r < r->tol) {
+          status = PMG_OK;
+        } else if (r->cycles >= r->max_cycles) {
+          status = PMG_ERR_NOT_CONVERGED;
+        } else {
+          r->ms.update(r->r, r->s->mg.mixed_patience > 0 ? r->s->mg.mixed_patience : 4);
+          r->cycle_next = true;
+        }
+      }
+      if (status >= 0) server_retire(sv, r, status);
+      else keep.push_back(r);
+    }
+    sv->resident.swap(keep);
+  }
+  for (auto& r : sv->resident) server_retire(sv, r, PMG_ERR_BUSY);
+  sv->resident.clear();
+}
+
+extern "C" {
+
+pmg_status pmg_footprint(pmg_mesh mesh, const int32_t* orders, const pmg_mg_params* mg, int64_t* bytes,
+                         int64_t* transient_bytes, int64_t* switch_bytes) {
+  return guard([&] {
+    REQUIRE(mesh && orders && bytes, "NULL argument");
+    for (int64_t i = 0; i < 3 * mesh->K; i++) REQUIRE(orders[i] >= 1 && orders[i] <= PMG_MAXN - 1, "orders must be 1..7");
+    double tr = 0.0, sw = 0.0;
+    *bytes = (int64_t)std::ceil(solver_footprint(mesh, orders, mg, &tr, &sw));
+    if (transient_bytes) *transient_bytes = (int64_t)std::ceil(tr);
+    if (switch_bytes) *switch_bytes = (int64_t)std::ceil(sw);
+  });
+}
+
+pmg_status pmg_device_bytes(int64_t* bytes) {
+  return guard([&] {
+    REQUIRE(bytes, "NULL argument");
+    *bytes = g_dev_bytes.load();
+  });
+}
+
+pmg_status pmg_server_create(pmg_ctx ctx, int64_t hbm_budget_bytes, int n_streams, int use_graph, pmg_server* out) {
+  return guard([&] {
+    REQUIRE(ctx && out, "NULL argument");
+    REQUIRE(hbm_budget_bytes > 0, "the HBM budget must be positive");
+    REQUIRE(n_streams >= 1 && n_streams <= 64, "n_streams must be 1..64");
+    HIPCHECK(hipSetDevice(ctx->device));
+    auto sv = std::make_unique<pmg_server_s>();
+    sv->ctx = ctx;
+    sv->budget = (double)hbm_budget_bytes;
+    sv->graph = use_graph ? 1 : 0;
+    for (int i = 0; i < n_streams; i++) {
+      hipStream_t st;
+      HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      sv->streams.push_back(st);
+    }
+    pmg_server_s* p = sv.get();
+    sv->worker = std::thread([p] { server_loop(p); });
+    *out = sv.release();
+  });
+}
+
+pmg_status pmg_server_submit(pmg_server sv, pmg_mesh mesh, const int32_t* orders, const pmg_physics* phys,
+                             const pmg_mg_params* mg, double* Q_dev, double tol, int max_cycles, uint64_t* ticket) {
+  return guard([&] {
+    REQUIRE(sv && mesh && orders && phys && Q_dev && ticket, "NULL argument");
+    REQUIRE(mesh->ctx == sv->ctx, "mesh belongs to another context");
+    REQUIRE(max_cycles >= 0, "negative max_cycles");
+    REQUIRE(!mg || (!mg->tuning && !mg->fmg), "served solves use fixed sweep counts and no FMG start");
+    for (int64_t i = 0; i < 3 * mesh->K; i++) REQUIRE(orders[i] >= 1 && orders[i] <= PMG_MAXN - 1, "orders must be 1..7");
+    auto r = std::make_shared<ServerReq>();
+    r->mesh = mesh;
+    r->orders.assign(orders, orders + 3 * mesh->K);
+    r->phys = *phys;
+    if (mg) {
+      r->mg = *mg;
+      if (mg->n_levels > 0 && mg->level_caps) r->caps.assign(mg->level_caps, mg->level_caps + mg->n_levels);
+    } else {
+      memset(&r->mg, 0, sizeof(r->mg));
+      r->mg.beta_pre = r->mg.beta_post = r->mg.beta_coarse = 3;
+      r->mg.eta = 1.1;
+      r->mg.max_repeats = 10;
+      r->mg.fmg_threshold = 0.1;
+    }
+    r->mg.level_caps = nullptr;
+    r->tol = tol;
+    r->max_cycles = max_cycles;
+    r->Q = Q_dev;
+    double tr = 0.0, sw = 0.0;
+    pmg_mg_params m = r->mg;
+    m.level_caps = r->caps.empty() ? nullptr : r->caps.data();
+    r->est = solver_footprint(mesh, orders, &m, &tr, &sw) + tr + sw;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    REQUIRE(sv->fatal.empty(), "server stopped: " + sv->fatal);
+    if (r->est > sv->budget)
+      throw PmgError(PMG_ERR_OOM, "request footprint " + std::to_string((long long)r->est) +
+                                      " B exceeds the server's HBM budget");
+    r->ticket = sv->next_ticket++;
+    r->t_submit = sv->now();
+    sv->queue.push_back(r);
+    sv->all[r->ticket] = r;
+    *ticket = r->ticket;
+    sv->cv.notify_one();
+  });
+}
+
+pmg_status pmg_server_poll(pmg_server sv, uint64_t ticket, int* done, int* status, int* cycles, int* fp32_cycles,
+                           double* res_inf, double* latency_s, double* queue_s) {
+  return guard([&] {
+    REQUIRE(sv && done, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->all.find(ticket);
+    REQUIRE(it != sv->all.end(), "unknown ticket");
+    const ServerReq& r = *it->second;
+    *done = r.done;
+    if (!r.done) return;
+    if (status) *status = r.status;
+    if (cycles) *cycles = r.cycles;
+    if (fp32_cycles) *fp32_cycles = r.fp32;
+    if (res_inf) *res_inf = r.r;
+    if (latency_s) *latency_s = r.t_done - r.t_submit;
+    if (queue_s) *queue_s = r.t_admit - r.t_submit;
+  });
+}
+
+pmg_status pmg_server_stats(pmg_server sv, int* resident, int* queued, int64_t* completed, int64_t* iterations,
+                            int64_t* bytes_in_use, int64_t* peak_bytes, int* max_resident) {
+  return guard([&] {
+    REQUIRE(sv, "NULL server");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (resident) *resident = (int)sv->resident.size();
+    if (queued) *queued = (int)sv->queue.size();
+    if (completed) *completed = sv->completed;
+    if (iterations) *iterations = sv->iterations;
+    if (bytes_in_use) *bytes_in_use = (int64_t)sv->used;
+    if (peak_bytes) *peak_bytes = (int64_t)sv->peak;
+    if (max_resident) *max_resident = sv->max_resident;
+    REQUIRE(sv->fatal.empty(), "server stopped: " + sv->fatal);
+  });
+}
+
+void pmg_server_destroy(pmg_server sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  for (hipStream_t st : sv->streams) (void)hipStreamDestroy(st);
+  delete sv;
 }
 
 pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, int isolated, double* tau_map_dev,

@@ -25,7 +25,8 @@ EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_crea
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
            "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
-           "pmg_level_tiles", "pmg_solve_stats"]
+           "pmg_level_tiles", "pmg_solve_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
+           "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy"]
 
 # kernel kinds of pmg_profile_enable / pmg_profile_read
 KINDS = {"trace": 0, "face1": 1, "grad": 2, "face2": 3, "div": 4, "dt": 5, "transfer": 6}
@@ -107,8 +108,19 @@ def lib():
     L.pmg_set_graph.argtypes = [P, C.c_int]
     L.pmg_autotune.argtypes = [P, V]
     L.pmg_level_tiles.argtypes = [P, C.c_int, C.c_int, I32]
+    L.pmg_solve_stats.argtypes = [P, I32]
+    L.pmg_footprint.argtypes = [P, I32, C.POINTER(MGParams), I64, I64, I64]
+    L.pmg_device_bytes.argtypes = [I64]
+    L.pmg_server_create.argtypes = [P, C.c_int64, C.c_int, C.c_int, pp]
+    L.pmg_server_submit.argtypes = [P, P, I32, C.POINTER(Physics), C.POINTER(MGParams), V, C.c_double, C.c_int,
+                                    C.POINTER(C.c_uint64)]
+    L.pmg_server_poll.argtypes = [P, C.c_uint64, I32, I32, I32, I32, D, D, D]
+    L.pmg_server_stats.argtypes = [P, I32, I32, I64, I64, I64, I64, I32]
+    L.pmg_server_destroy.argtypes = [P]
+    L.pmg_server_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("pmg_last_error", "pmg_ctx_destroy", "pmg_mesh_destroy", "pmg_solver_destroy"):
+        if name not in ("pmg_last_error", "pmg_ctx_destroy", "pmg_mesh_destroy", "pmg_solver_destroy",
+                        "pmg_server_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -167,6 +179,34 @@ class Mesh:
             self.h = None
 
 
+def mg_struct(mg):
+    """(pmg_mg_params, level-caps array that must outlive the call)."""
+    caps = None if mg.level_caps is None else np.asarray(mg.level_caps, dtype=np.int32)
+    p = MGParams(0 if caps is None else len(caps),
+                 None if caps is None else caps.ctypes.data_as(C.POINTER(C.c_int32)),
+                 mg.beta_pre, mg.beta_post, mg.beta_coarse, mg.tuning, mg.eta, mg.max_repeats, mg.fmg,
+                 mg.fmg_threshold, mg.precision, mg.mixed_patience)
+    return p, caps
+
+
+def footprint(mesh: "Mesh", orders, mg: "MG" = None):
+    """(device bytes as built, construction transient, precision-switch hierarchy) of a single-problem
+    solver (pmg_footprint)."""
+    orders = np.ascontiguousarray(orders, dtype=np.int32)
+    p, caps = mg_struct(mg or MG())
+    b, t, sw = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().pmg_footprint(mesh.h, orders.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(p), C.byref(b),
+                               C.byref(t), C.byref(sw)))
+    return int(b.value), int(t.value), int(sw.value)
+
+
+def device_bytes() -> int:
+    """Device bytes currently allocated by the library."""
+    b = C.c_int64()
+    _check(lib().pmg_device_bytes(C.byref(b)))
+    return int(b.value)
+
+
 def physics_struct(ph) -> Physics:
     return Physics(ph.mach, ph.reynolds, ph.prandtl, ph.gamma, ph.sutherland, ph.cfl_adv, ph.cfl_visc,
                    int(ph.family), int(ph.viscosity))
@@ -186,12 +226,8 @@ class Solver:
         self.mesh, self.phys = mesh, phys
 
     def _params(self, mg):
-        caps = None if mg.level_caps is None else np.asarray(mg.level_caps, dtype=np.int32)
-        self._caps = caps
-        return MGParams(0 if caps is None else len(caps),
-                        None if caps is None else caps.ctypes.data_as(C.POINTER(C.c_int32)),
-                        mg.beta_pre, mg.beta_post, mg.beta_coarse, mg.tuning, mg.eta, mg.max_repeats, mg.fmg,
-                        mg.fmg_threshold, mg.precision, mg.mixed_patience)
+        p, self._caps = mg_struct(mg)
+        return p
 
     def _setup(self, ctx, h, K, orders, mg):
         import torch
@@ -355,3 +391,58 @@ class Batch(Solver):
     def part(self, U, p: int):
         """View of problem p's nodes in a batch array [5][n_nodes]."""
         return U[:, int(self.problem_offsets[p]):int(self.problem_offsets[p + 1])]
+
+
+class Server:
+    """Continuous-batching steady-solve server on one GPU (pmg_server_* in include/pmg.h).
+
+    submit() hands over a problem and a CUDA state tensor solved in place; poll() returns None while the
+    request is queued or resident, then a dict with status, cycles, fp32_cycles, residual, latency_s and
+    queue_s (seconds from submission to admission)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, n_streams: int = 4, use_graph: bool = True):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().pmg_server_create(ctx.h, int(hbm_budget_bytes), int(n_streams), int(bool(use_graph)),
+                                       C.byref(h)))
+        self.h = h
+        self._alive = {}  # ticket -> (mesh, state): kept alive until the request is done
+
+    def submit(self, mesh: Mesh, orders, phys, mg: MG, Q, tol: float, max_cycles: int) -> int:
+        import torch
+        orders = np.ascontiguousarray(orders, dtype=np.int32)
+        p, caps = mg_struct(mg)
+        ph = physics_struct(phys)
+        torch.cuda.current_stream().synchronize()  # the initial state is complete before the server reads it
+        t = C.c_uint64()
+        _check(lib().pmg_server_submit(self.h, mesh.h, orders.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(ph),
+                                       C.byref(p), _ptr(Q), float(tol), int(max_cycles), C.byref(t)))
+        self._alive[t.value] = (mesh, Q)
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        done, st, cyc, f32 = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        r, lat, qs = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().pmg_server_poll(self.h, C.c_uint64(ticket), C.byref(done), C.byref(st), C.byref(cyc),
+                                     C.byref(f32), C.byref(r), C.byref(lat), C.byref(qs)))
+        if not done.value:
+            return None
+        self._alive.pop(ticket, None)
+        return {"status": int(st.value), "cycles": int(cyc.value), "fp32_cycles": int(f32.value),
+                "residual": float(r.value), "latency_s": float(lat.value), "queue_s": float(qs.value)}
+
+    def stats(self):
+        res, q, mres = C.c_int32(), C.c_int32(), C.c_int32()
+        comp, it, used, peak = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().pmg_server_stats(self.h, C.byref(res), C.byref(q), C.byref(comp), C.byref(it), C.byref(used),
+                                      C.byref(peak), C.byref(mres)))
+        return {"resident": res.value, "queued": q.value, "completed": comp.value, "iterations": it.value,
+                "bytes_in_use": used.value, "peak_bytes": peak.value, "max_resident": mres.value}
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pmg_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
