@@ -45,6 +45,100 @@ def cpu_baseline(wl, evals: int):
                       f"one thread, {dt:.1f} s)"}
 
 
+def serve_bench(args) -> dict:
+    """Served stream (configuration 5 recipe, reduced sizes): Poisson arrivals at 20/s of steady-solve
+    requests on random stretched boxes with a wall, solved to ||r||_inf < 1e-9 by the continuous-batching
+    server; baseline: the same list solved one after another with pmg_solve (plain FP64) on the same GPU,
+    queued first come, first served at the same arrival times.  Both include solver construction."""
+    import numpy as np
+    import torch
+
+    from paper_1806_11456_amd import inputs as I
+    from paper_1806_11456_amd import pmg
+
+    reqs = I.config_serve(n=args.serve_n, seed=5, rate=20.0, kmin=args.serve_kmin, kmax=args.serve_kmax, lo=1,
+                          hi=4, re_lo=1e3, re_hi=1e4, ogrid_frac=0.0)
+    ctx = pmg.Context(0)
+    mg = pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4, precision=args.serve_precision)
+    meshes = [pmg.Mesh(ctx, w.mesh) for _, w, _ in reqs]
+    max_cycles = 20000
+
+    # served
+    states = [torch.tensor(w.Q, dtype=torch.float64, device="cuda") for _, w, _ in reqs]
+    torch.cuda.synchronize()
+    sv = pmg.Server(ctx, int(args.serve_budget_gib * 2 ** 30), n_streams=args.serve_streams, use_graph=True)
+    t0 = time.perf_counter()
+    tickets = []
+    for (arr, w, tol), m, Q in zip(reqs, meshes, states):
+        dt = t0 + arr - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(sv.submit(m, w.orders, w.phys, mg, Q, tol=tol, max_cycles=max_cycles))
+    done = {}
+    last = t0
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                r = sv.poll(t)
+                if r is not None:
+                    done[t] = r
+                    last = time.perf_counter()
+                    print(f"served {len(done)}/{len(tickets)}: {r}", file=sys.stderr, flush=True)
+        time.sleep(0.001)
+    stats = sv.stats()
+    sv.close()
+    served = [done[t] for t in tickets]
+    lat = np.array([r["latency_s"] for r in served])
+    ok = sum(r["status"] == 0 for r in served)
+
+    # baseline: sequential plain FP64 solves
+    solve_t = []
+    base_ok = 0
+    for (arr, w, tol), m in zip(reqs, meshes):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s = pmg.Solver(ctx, m, w.orders, w.phys, pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4))
+        s.set_graph(True)
+        Q = s.tensor(w.Q)
+        cyc, r = s.solve(Q, None, tol=tol, max_cycles=max_cycles, raise_not_converged=False)
+        torch.cuda.synchronize()
+        solve_t.append(time.perf_counter() - a)
+        base_ok += r < tol
+        print(f"sequential {len(solve_t)}/{len(reqs)}: {cyc} cycles, {solve_t[-1]:.2f} s", file=sys.stderr,
+              flush=True)
+        del s, Q
+    end = 0.0
+    blat = []
+    for (arr, _, _), d in zip(reqs, solve_t):
+        start = max(arr, end)
+        end = start + d
+        blat.append(end - arr)
+    blat = np.array(blat)
+    pct = lambda x, q: float(np.percentile(x, q))
+    return {
+        "metric": "p50/p99 latency (arrival to result); solves/s",
+        "value": pct(lat, 50),
+        "unit": "s",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "dtype": "f64" if args.serve_precision == 0 else "mixed f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"served stream: {len(reqs)} requests, Poisson arrivals 20/s (seed 5), random "
+                               f"stretched boxes K {args.serve_kmin}..{args.serve_kmax} with a no-slip wall and far "
+                               "field, orders U{1..4} per direction, Mach U[0.1,0.4], Re U[1e3,1e4], tol 1e-9, "
+                               "V-cycles beta 2/2/4",
+                   "dof_total": int(sum(w.n_nodes for _, w, _ in reqs)), "streams": args.serve_streams,
+                   "hbm_budget_gib": args.serve_budget_gib},
+        "served": {"p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "solves_per_s": len(reqs) / (last - t0),
+                   "makespan_s": last - t0, "converged": ok, "cycles_total": int(sum(r["cycles"] for r in served)),
+                   "max_resident": stats["max_resident"], "peak_bytes": stats["peak_bytes"],
+                   "iterations": stats["iterations"]},
+        "sequential_fp64": {"p50_s": pct(blat, 50), "p99_s": pct(blat, 99), "solves_per_s": len(reqs) / end,
+                            "makespan_s": end, "converged": int(base_ok),
+                            "solve_s_mean": float(np.mean(solve_t))},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +150,13 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--serve", action="store_true", help="served-stream latency benchmark instead of the plate")
+    ap.add_argument("--serve-n", type=int, default=24)
+    ap.add_argument("--serve-kmin", type=int, default=64)
+    ap.add_argument("--serve-kmax", type=int, default=400)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-precision", type=int, default=0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -63,6 +164,10 @@ def main() -> int:
             print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
                   f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
         return 2
+
+    if args.serve:
+        print(json.dumps(serve_bench(args)), flush=True)
+        return 0
 
     import numpy as np
     import torch

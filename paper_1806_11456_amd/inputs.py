@@ -517,6 +517,45 @@ def config_batch(n: int = 64, kmin: int = 2000, kmax: int = 20000, seed: int = 4
     return out
 
 
+def config_serve(n: int = 200, seed: int = 5, rate: float = 20.0, kmin: int = 1000, kmax: int = 50000,
+                 lo: int = 1, hi: int = 7, re_lo: float = 1e2, re_hi: float = 1e4, tol: float = 1e-9,
+                 ogrid_frac: float = 0.5):
+    """A served stream of steady-solve requests: Poisson arrival times at 'rate' per second; each request a
+    random stretched box as in config_batch (K ~ U{kmin..kmax}) or, with probability ogrid_frac, a six-block
+    O-grid around the unit sphere (6 nt^2 nr ~ K hexes, outer radius 20, rotated frames); orders iid in
+    [lo, hi] per direction; Mach in [0.1, 0.4], Re in [re_lo, re_hi]; far-field start.  Returns a list of
+    (arrival time in seconds, Workload, tol), all from the seed."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for q in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        K = int(rng.integers(kmin, kmax + 1))
+        mach = float(rng.uniform(0.1, 0.4))
+        re = float(rng.uniform(re_lo, re_hi))
+        if rng.uniform() >= ogrid_frac:
+            a = rng.uniform(0.5, 2.0, size=2)
+            nz = max(1, int(round(K ** (1 / 3))))
+            nx = max(1, int(round((K / nz) ** 0.5 * a[0] / a[1])))
+            ny = max(1, int(round(K / (nx * nz))))
+            ratio = float(rng.uniform(1.0, 1.15))
+            mesh = box_mesh((nx, ny, nz), (0.0, 0.0, 0.0),
+                            (1.0 * nx / max(nx, ny), 1.0 * ny / max(nx, ny), 0.1 * nz),
+                            M=(1, 1, 1), periodic=(False, False, True), ratio=(1.0, ratio, 1.0),
+                            bc_lo=(BC_FARFIELD, BC_WALL, BC_NONE), bc_hi=(BC_FARFIELD, BC_FARFIELD, BC_NONE),
+                            name=f"serve{q}_box")
+        else:
+            nr = max(2, int(round((K / 6.0) ** (1 / 3) * rng.uniform(0.8, 1.25))))
+            nt = max(1, int(round((K / (6.0 * nr)) ** 0.5)))
+            mesh, _ = reorient(ogrid_mesh(nt, nr, r_out=20.0, ratio=1.25, name=f"serve{q}_ogrid"),
+                               int(rng.integers(1 << 30)))
+        orders = rng.integers(lo, hi + 1, size=(mesh.K, 3)).astype(np.int32)
+        phys = Physics(mach=mach, reynolds=re, family=FAMILY_LG, cfl_adv=0.2, cfl_visc=0.2)
+        n_nodes = int(node_offsets(orders)[-1])
+        out.append((t, Workload(mesh.name, mesh, orders, phys, freestream_state(n_nodes, mach)), tol))
+    return out
+
+
 def config_ogrid(nt: int = 8, nr: int = 13, seed: int = 3, lo: int = 1, hi: int = 7, amp: float = 1e-3,
                  r_out: float = 20.0, ratio: float = 1.25, cfl: float = 0.2) -> Workload:
     """Six-block O-grid around the unit sphere (outer radius 20), quadratic mapping, iid orders in [lo,hi].
