@@ -190,6 +190,32 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
  */
 pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, int isolated, double* tau_map_dev,
                             void* stream);
+/* Residual history of the last pmg_solve: ||r||_inf at every check (the start and after each cycle).  n
+ * receives the number of entries; at most 'capacity' are copied to out (host). */
+pmg_status pmg_solve_history(pmg_solver s, double* out, int32_t capacity, int32_t* n);
+/* V-cycles run on the solver's state since creation or the last restore (pmg_vcycle, pmg_solve). */
+pmg_status pmg_cycle_count(pmg_solver s, int64_t* cycles);
+/*
+ * Checkpoint / resume.  pmg_checkpoint writes to 'path' (through 'path'.tmp and a rename) the fine state
+ * Q_dev, the orders, the cycle counter and the residual history, with a checksum; every coarse level is
+ * rebuilt from the fine state by each cycle, so nothing else carries over.  pmg_restore checks the file
+ * (checksum, same mesh size, orders and problem count, else PMG_ERR_INVALID_ARG) and writes the state into
+ * Q_dev: cycles run from it reproduce, bitwise, those run from the state that was saved.
+ */
+pmg_status pmg_checkpoint(pmg_solver s, const char* path, const double* Q_dev, void* stream);
+pmg_status pmg_restore(pmg_solver s, const char* path, double* Q_dev, void* stream);
+
+/*
+ * Pointwise truncation error of one anisotropic level (Sec. 3.2.3; the quantity the tau map reduces): runs
+ * the anisotropic V-cycle of direction dir on Q_dev (as pmg_tau_estimate does for that direction, so Q_dev
+ * is updated by that one cycle) and writes tau = S_phys - A(Q~0) (isolated = 0) or S_phys - A^(Q~0)
+ * (isolated = 1) of the level whose order in dir is capped at 'order' (1 <= order < max order in dir) into
+ * tau_dev, layout [5][n_nodes of that level] (pmg_level_info(dir, level) gives the level's orders; elements
+ * in user order).  Elements whose order in dir is at most 'order' are not coarsened there and hold the
+ * residual of the restricted state.
+ */
+pmg_status pmg_tau_nodal(pmg_solver s, int dir, int order, double* Q_dev, const double* S_dev, int isolated,
+                         double* tau_dev, void* stream);
 
 /*
  * Batches of independent steady problems (many solves advanced together by the same V-cycle).  The n

@@ -158,6 +158,31 @@ void ora_tau_3v(or_problem* P, const int32_t* ord, const or_mg_params* prm, doub
   }
 }
 
+/* One anisotropic V-cycle in direction d (levels max N_d down to 1, as in ora_tau_3v) that also copies the
+ * pointwise truncation error of the level capped at 'cap' into tau_nodal ([5][nn of that level]). */
+void ora_tau_nodal(or_problem* P, const int32_t* ord, const or_mg_params* prm, double* Q, const double* S, int d,
+                   int cap, double* tau_nodal) {
+  int64_t K = P->K;
+  int pmax = 1;
+  for (int64_t e = 0; e < K; e++)
+    if (ord[3 * e + d] > pmax) pmax = ord[3 * e + d];
+  int nlev = pmax;
+  if (nlev < 2) return;
+  int nt = pmax - 1;
+  double* tau_map = malloc(sizeof(double) * K * 3 * nt);
+  for (int64_t i = 0; i < K * 3 * nt; i++) tau_map[i] = NAN;
+  int* caps = malloc(sizeof(int) * nlev);
+  for (int l = 0; l < nlev; l++) caps[l] = pmax - l;
+  or_mg* mg = or_mg_create(P, ord, nlev, caps, d);
+  mg->tau_nodal = tau_nodal;
+  mg->tau_nodal_cap = cap;
+  or_mg_vcycles(P, mg, Q, S, 1, prm, tau_map, nt);
+  mg->tau_nodal = NULL;
+  or_mg_destroy(mg);
+  free(caps);
+  free(tau_map);
+}
+
 int ora_solve(or_problem* P, const int32_t* ord, int nlev, const int32_t* caps, const or_mg_params* prm, double* Q,
               const double* S, double tol, int max_cycles, double* res_out, double* history) {
   int* c = malloc(sizeof(int) * nlev);

@@ -233,6 +233,7 @@ static void vcycle(const or_problem* P, or_mg* mg, int l, int top, const or_mg_p
       if (prm->isolated) or_operator(P, L, 1, mg->Q[l], tmp);
       for (int64_t i = 0; i < n; i++) tmp[i] = mg->Sphys[l][i] - tmp[i];
       record_tau(P, mg, l, tmp, tau_map, nt);
+      if (mg->tau_nodal && mg->caps[l] == mg->tau_nodal_cap) memcpy(mg->tau_nodal, tmp, sizeof(double) * n);
     }
   }
   memcpy(mg->Q0[l], mg->Q[l], sizeof(double) * n);

@@ -73,6 +73,7 @@ def lib():
         L.ora_vcycles.restype = C.c_double
         L.ora_vcycles.argtypes = [P, I32, C.c_int, I32, C.c_int, C.POINTER(MGParams), D, D, C.c_int]
         L.ora_tau_3v.argtypes = [P, I32, C.POINTER(MGParams), D, D, D, C.c_int]
+        L.ora_tau_nodal.argtypes = [P, I32, C.POINTER(MGParams), D, D, C.c_int, C.c_int, D]
         L.ora_rk3_linear.restype = C.c_double
         L.ora_rk3_linear.argtypes = [C.c_double, C.c_double, C.c_double]
         L.ora_gradient.argtypes = [P, I32, C.c_int, D, D]
@@ -249,6 +250,20 @@ class Oracle:
         Sp = _d(_f64(S)) if S is not None else None
         p = mg_params(**prm)
         lib().ora_tau_3v(self.h, _i32(orders), C.byref(p), _d(Q), Sp, _d(tau), nt)
+        return tau, Q
+
+    def tau_nodal(self, orders, Q, S=None, d=0, cap=1, **prm):
+        """One anisotropic V-cycle in direction d; returns (pointwise tau [5][nn] of the level whose order in d
+        is capped at 'cap', state after the cycle)."""
+        orders = self._ord(orders)
+        o = orders.copy()
+        o[:, d] = np.minimum(o[:, d], cap)
+        nn = int(np.prod(o + 1, axis=1).sum())
+        tau = np.full((5, nn), np.nan)
+        Q = np.array(Q, dtype=np.float64, copy=True)
+        Sp = _d(_f64(S)) if S is not None else None
+        p = mg_params(**prm)
+        lib().ora_tau_nodal(self.h, _i32(orders), C.byref(p), _d(Q), Sp, int(d), int(cap), _d(tau))
         return tau, Q
 
     def solve(self, orders, Q, S=None, caps=None, tol=1e-9, max_cycles=100, **prm):

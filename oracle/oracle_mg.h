@@ -20,6 +20,9 @@ typedef struct {
   int* caps; /* per level index (0 = coarsest) */
   or_level** L;
   double **Q, **Q0, **S, **r, **Sphys;
+  /* optional copy of the pointwise truncation error [5][nn] of the level whose cap is tau_nodal_cap */
+  double* tau_nodal;
+  int tau_nodal_cap;
 } or_mg;
 
 void or_residual(const or_problem* P, const or_level* L, int isolated, const double* Q, const double* S, double* R);

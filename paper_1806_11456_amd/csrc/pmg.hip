@@ -278,6 +278,9 @@ struct pmg_solver_s {
   std::unique_ptr<Hier> iso64;               // FP64 isotropic hierarchy of a mixed-precision solver
   std::vector<int> fp32_cycles;              // per problem: cycles of the last solve with FP32 coarse levels
   std::vector<int> iso_caps;                 // order caps of the isotropic levels, finest first
+  double* d_taumap = nullptr;                // scratch tau map of pmg_tau_nodal
+  std::vector<double> history;               // residual checks of the last pmg_solve
+  int64_t cycles_total = 0;                  // V-cycles run on the state since creation or restore
   unsigned long long* d_red = nullptr;       // reduction slots [NSLOTS][nprob]
   double* d_zero = nullptr;                  // [5][nn] zeros (absent source)
   double* d_R = nullptr;                     // [5][nn] top-level scratch residual
@@ -820,6 +823,8 @@ struct TauRec {
   double* map;
   int nt;
   int isolated;
+  double* nodal = nullptr;  // optional pointwise tau of one (direction, cap) level
+  int nodal_dir = -1, nodal_cap = 0;
 };
 
 struct CycleCtx {
@@ -902,7 +907,12 @@ static void coarse_source(CycleCtx& c, int l) {
   a.S = (const T*)H.r[l];
   a.out = (T*)H.S[l];
   const bool rec = c.tau != nullptr;
+  T* nodal = nullptr;
+  if (rec && c.tau->nodal && H.dir == c.tau->nodal_dir && H.caps[l] == c.tau->nodal_cap) {
+    if constexpr (std::is_same<T, double>::value) nodal = c.tau->nodal;
+  }
   if (rec && !c.tau->isolated) {
+    a.tau_out = nodal;
     a.Sphys = (const T*)H.Sp[l];
     a.tau_map = c.tau->map;
     a.tau_dir = H.dir;
@@ -913,6 +923,7 @@ static void coarse_source(CycleCtx& c, int l) {
   op_eval(s, L, (const T*)H.Q[l], false, a, c.st, c.act);
   if (rec && c.tau->isolated) {
     DivArgs<T> t = div_args<T>(EPI_TAU);
+    t.tau_out = nodal;
     t.Sphys = (const T*)H.Sp[l];
     t.tau_map = c.tau->map;
     t.tau_dir = H.dir;
@@ -1529,6 +1540,7 @@ pmg_status pmg_vcycle(pmg_solver s, double* Q_dev, const double* S_dev, int n_cy
     } else {
       run_vcycles(s, s->iso, Q_dev, S_dev, n_cycles, nullptr, st);
     }
+    s->cycles_total += n_cycles;
     HIPCHECK(hipGetLastError());
     if (res_inf_host) {
       residual(s, *s->top, Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
@@ -1600,9 +1612,11 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
     H->Q[top] = nullptr;
     MixedState ms;
     ms.f32 = mixed;
+    s->history.clear();
     for (;;) {
       residual(s, *s->top, (const double*)Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
       r = read_slot(s, SLOT_NORM, st);
+      s->history.push_back(r);
       if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
       if (r < tol || cycles >= max_cycles) break;
       ms.update(r, patience);
@@ -1614,6 +1628,7 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
         cycle_once(s, ms.f32 ? s->iso : iso_f64(s), ms.f32 ? 0 : 2, Q_dev, S_dev, nullptr, st);
       }
       cycles++;
+      s->cycles_total++;
       c32 += ms.f32;
     }
     s->fp32_cycles.assign(s->nprob, c32);
@@ -1984,6 +1999,138 @@ pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, in
     } else {
       tau_cycles(s, Q_dev, S_dev, tau, st);
     }
+    HIPCHECK(hipGetLastError());
+  });
+}
+
+// ------------------------------------------------------------------------------------------------
+// Residual history, checkpoint and restore
+// ------------------------------------------------------------------------------------------------
+pmg_status pmg_solve_history(pmg_solver s, double* out, int32_t capacity, int32_t* n) {
+  return guard([&] {
+    REQUIRE(s && n, "NULL argument");
+    REQUIRE(capacity >= 0 && (capacity == 0 || out), "bad output buffer");
+    *n = (int32_t)s->history.size();
+    for (int i = 0; i < std::min<int>(capacity, (int)s->history.size()); i++) out[i] = s->history[i];
+  });
+}
+
+static uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  for (size_t i = 0; i < n; i++) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+static const char kCkptMagic[8] = {'P', 'M', 'G', 'C', 'K', 'P', 'T', '1'};
+
+pmg_status pmg_checkpoint(pmg_solver s, const char* path, const double* Q_dev, void* stream) {
+  return guard([&] {
+    REQUIRE(s && path && Q_dev, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t K = s->mesh->K, nn = s->top->nn, nh = (int64_t)s->history.size();
+    std::vector<unsigned char> buf;
+    auto put = [&](const void* p, size_t n) {
+      const unsigned char* c = (const unsigned char*)p;
+      buf.insert(buf.end(), c, c + n);
+    };
+    put(kCkptMagic, 8);
+    put(&K, 8);
+    put(&nn, 8);
+    put(&s->nprob, 4);
+    put(s->orders.data(), sizeof(int) * s->orders.size());
+    put(&s->cycles_total, 8);
+    put(&nh, 8);
+    put(s->history.data(), sizeof(double) * nh);
+    std::vector<double> Q(5 * (size_t)nn);
+    HIPCHECK(hipMemcpyAsync(Q.data(), Q_dev, Q.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    put(Q.data(), Q.size() * sizeof(double));
+    uint64_t h = fnv1a(buf.data(), buf.size());
+    put(&h, 8);
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    REQUIRE(f, std::string("cannot open ") + tmp);
+    size_t w = fwrite(buf.data(), 1, buf.size(), f);
+    int cl = fclose(f);
+    REQUIRE(w == buf.size() && cl == 0, std::string("short write to ") + tmp);
+    REQUIRE(rename(tmp.c_str(), path) == 0, std::string("cannot rename to ") + path);
+  });
+}
+
+pmg_status pmg_restore(pmg_solver s, const char* path, double* Q_dev, void* stream) {
+  return guard([&] {
+    REQUIRE(s && path && Q_dev, "NULL argument");
+    FILE* f = fopen(path, "rb");
+    REQUIRE(f, std::string("cannot open ") + path);
+    std::vector<unsigned char> buf;
+    unsigned char chunk[1 << 16];
+    size_t got;
+    while ((got = fread(chunk, 1, sizeof(chunk), f)) > 0) buf.insert(buf.end(), chunk, chunk + got);
+    fclose(f);
+    size_t pos = 0;
+    auto take = [&](void* p, size_t n) {
+      REQUIRE(pos + n <= buf.size(), "checkpoint file is truncated");
+      memcpy(p, buf.data() + pos, n);
+      pos += n;
+    };
+    REQUIRE(buf.size() >= 16, "checkpoint file is truncated");
+    uint64_t h_file;
+    memcpy(&h_file, buf.data() + buf.size() - 8, 8);
+    REQUIRE(fnv1a(buf.data(), buf.size() - 8) == h_file, "checkpoint checksum mismatch");
+    char magic[8];
+    take(magic, 8);
+    REQUIRE(memcmp(magic, kCkptMagic, 8) == 0, "not a checkpoint of this library");
+    int64_t K, nn, cyc, nh;
+    int32_t np;
+    take(&K, 8);
+    take(&nn, 8);
+    take(&np, 4);
+    REQUIRE(K == s->mesh->K && nn == s->top->nn && np == s->nprob, "checkpoint is of another problem");
+    std::vector<int> ord(s->orders.size());
+    take(ord.data(), sizeof(int) * ord.size());
+    REQUIRE(ord == s->orders, "checkpoint has other orders");
+    take(&cyc, 8);
+    take(&nh, 8);
+    REQUIRE(nh >= 0 && nh < (1ll << 40), "bad history length");
+    std::vector<double> hist((size_t)nh);
+    take(hist.data(), sizeof(double) * nh);
+    std::vector<double> Q(5 * (size_t)nn);
+    take(Q.data(), Q.size() * sizeof(double));
+    REQUIRE(pos + 8 == buf.size(), "checkpoint has trailing bytes");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHECK(hipMemcpyAsync(Q_dev, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    s->cycles_total = cyc;
+    s->history = hist;
+  });
+}
+
+pmg_status pmg_cycle_count(pmg_solver s, int64_t* cycles) {
+  return guard([&] {
+    REQUIRE(s && cycles, "NULL argument");
+    *cycles = s->cycles_total;
+  });
+}
+
+pmg_status pmg_tau_nodal(pmg_solver s, int dir, int order, double* Q_dev, const double* S_dev, int isolated,
+                         double* tau_dev, void* stream) {
+  return guard([&] {
+    REQUIRE(s && Q_dev && tau_dev, "NULL argument");
+    REQUIRE(dir >= 0 && dir <= 2, "dir must be 0, 1 or 2");
+    Hier& H = aniso_hier(s, dir);
+    int lev = -1;
+    for (int l = 0; l + 1 < (int)H.lv.size(); l++)
+      if (H.caps[l] == order) lev = l;
+    REQUIRE(lev >= 0, "no coarse level with that order in that direction (1 <= order < max order in dir)");
+    hipStream_t st = (hipStream_t)stream;
+    if (!s->d_taumap) s->d_taumap = s->arena.alloc<double>((size_t)s->mesh->K * 3 * std::max(s->nmax - 1, 1));
+    TauRec tau{s->d_taumap, std::max(s->nmax - 1, 1), isolated ? 1 : 0};
+    tau.nodal = tau_dev;
+    tau.nodal_dir = dir;
+    tau.nodal_cap = order;
+    run_vcycles(s, H, Q_dev, S_dev, 1, &tau, st);
     HIPCHECK(hipGetLastError());
   });
 }

@@ -26,7 +26,8 @@ EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_crea
            "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
            "pmg_level_tiles", "pmg_solve_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
-           "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy"]
+           "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy", "pmg_tau_nodal",
+           "pmg_solve_history", "pmg_cycle_count", "pmg_checkpoint", "pmg_restore"]
 
 # kernel kinds of pmg_profile_enable / pmg_profile_read
 KINDS = {"trace": 0, "face1": 1, "grad": 2, "face2": 3, "div": 4, "dt": 5, "transfer": 6}
@@ -98,6 +99,11 @@ def lib():
     L.pmg_vcycle.argtypes = [P, V, V, C.c_int, D, V]
     L.pmg_solve.argtypes = [P, V, V, C.c_double, C.c_int, I32, D, V]
     L.pmg_tau_estimate.argtypes = [P, V, V, C.c_int, V, V]
+    L.pmg_tau_nodal.argtypes = [P, C.c_int, C.c_int, V, V, C.c_int, V, V]
+    L.pmg_solve_history.argtypes = [P, D, C.c_int32, I32]
+    L.pmg_cycle_count.argtypes = [P, I64]
+    L.pmg_checkpoint.argtypes = [P, C.c_char_p, V, V]
+    L.pmg_restore.argtypes = [P, C.c_char_p, V, V]
     L.pmg_profile_enable.argtypes = [P, C.c_uint32]
     L.pmg_profile_read.argtypes = [P, C.c_int, D, I64, D]
     L.pmg_batch_create.argtypes = [P, C.c_int, C.POINTER(C.c_void_p), C.POINTER(I32), C.POINTER(Physics),
@@ -339,6 +345,37 @@ class Solver:
         tau = self.torch.empty((self.K, 3, nt), dtype=self.torch.float64, device=self.device)
         _check(lib().pmg_tau_estimate(self.h, _ptr(Q), _ptr(S), int(bool(isolated)), _ptr(tau), _stream()))
         return tau
+
+    def history(self):
+        """||r||_inf at every check of the last solve()."""
+        n = C.c_int32()
+        _check(lib().pmg_solve_history(self.h, None, 0, C.byref(n)))
+        out = np.zeros(n.value)
+        _check(lib().pmg_solve_history(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n.value, C.byref(n)))
+        return out
+
+    def cycle_count(self) -> int:
+        c = C.c_int64()
+        _check(lib().pmg_cycle_count(self.h, C.byref(c)))
+        return int(c.value)
+
+    def checkpoint(self, path: str, Q):
+        _check(lib().pmg_checkpoint(self.h, str(path).encode(), _ptr(Q), _stream()))
+
+    def restore(self, path: str, Q):
+        _check(lib().pmg_restore(self.h, str(path).encode(), _ptr(Q), _stream()))
+
+    def tau_nodal(self, Q, S=None, d=0, order=1, isolated=True):
+        """Pointwise tau [5][nn] of the level of hierarchy d capped at 'order' (one anisotropic cycle on Q)."""
+        import torch
+        nl = self.level_info(d)
+        lev = [l for l in range(nl - 1) if int(self.level_info(d, l)[1][:, d].max()) == order]
+        assert lev, "no such level"
+        nn = self.level_info(d, lev[0])[0]
+        out = torch.empty((5, nn), dtype=torch.float64, device=self.device)
+        _check(lib().pmg_tau_nodal(self.h, int(d), int(order), _ptr(Q), _ptr(S), int(bool(isolated)), _ptr(out),
+                                   _stream()))
+        return out
 
     def set_graph(self, enable: bool):
         _check(lib().pmg_set_graph(self.h, int(bool(enable))))

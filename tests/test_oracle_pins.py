@@ -455,3 +455,25 @@ def test_plate_z_uniform(oracle_mod):
     for e in range(wl.mesh.K):
         r = R[:, off[e]:off[e + 1]].reshape(5, 2, 7, 7)
         assert np.abs(r[:, 0] - r[:, 1]).max() < 1e-9 * np.abs(R).max()
+
+
+def test_tau_nodal_reduces_to_tau_map(oracle_mod):
+    """The pointwise truncation error of one anisotropic cycle reduces (max over an element's nodes and the
+    variables) to that cycle's entry of the per-direction tau map, and running the three directions one
+    after another reproduces the 3V state; both the non-isolated and the isolated forms."""
+    O = oracle_mod
+    w = I.config_box()
+    o = O.Oracle(w.mesh, w.phys)
+    prm = dict(beta_pre=1, beta_post=1, beta_coarse=1)
+    for iso in (0, 1):
+        tau_map, Q3 = o.tau_3v(w.orders, w.Q, None, isolated=iso, **prm)
+        for cap in (1, 2):
+            Q = w.Q
+            for d in range(3):
+                tn, Q = o.tau_nodal(w.orders, Q, None, d=d, cap=cap, isolated=iso, **prm)
+                o2 = w.orders.copy()
+                o2[:, d] = np.minimum(o2[:, d], cap)
+                off = I.node_offsets(o2)
+                m = np.array([np.abs(tn[:, off[e]:off[e + 1]]).max() for e in range(w.mesh.K)])
+                assert np.array_equal(m, tau_map[:, d, cap - 1]), (iso, cap, d)
+            assert np.array_equal(Q, Q3)
