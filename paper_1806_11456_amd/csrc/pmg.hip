@@ -439,16 +439,27 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_J = A.alloc<double>(nn);
   L->d_Nout = A.alloc<double>(3 * nf);
   L->d_mgeo = A.alloc<double>(4 * (size_t)std::max(L->nm, 1));
-  auto alloc_work = [&](auto& W) {
-    using T = std::remove_pointer_t<decltype(W.qf)>;
-    W.qf = A.alloc<T>(5 * nf);
-    W.Ws = A.alloc<T>(4 * nf);
-    W.gW = A.alloc<T>(12 * nn);
-    W.gf = A.alloc<T>(12 * nf);
-    W.PhiA = A.alloc<T>(5 * nf);
-    W.Phi = A.alloc<T>(5 * nf);
-  };
-  if (prec == PREC_F32) alloc_work(L->w32); else alloc_work(L->w64);
+  // Operator work arrays live only during one evaluation on one level, and every level of a solver runs on
+  // one stream: the finest level allocates them (FP64) and every coarser level of every hierarchy aliases
+  // them, never larger (capped orders give fewer nodes, face nodes and mortar nodes per element), FP32
+  // levels in half the bytes.
+  if (!s->top) {
+    REQUIRE(prec == PREC_F64, "the finest level is FP64");
+    Work<double>& W = L->w64;
+    W.qf = A.alloc<double>(5 * nf);
+    W.Ws = A.alloc<double>(4 * nf);
+    W.gW = A.alloc<double>(12 * nn);
+    W.gf = A.alloc<double>(12 * nf);
+    W.PhiA = A.alloc<double>(5 * nf);
+    W.Phi = A.alloc<double>(5 * nf);
+  } else {
+    const Work<double>& T = s->top->w64;
+    REQUIRE(nn <= s->top->nn && nf <= s->top->nf, "coarse level larger than the finest");
+    if (prec == PREC_F32)
+      L->w32 = Work<float>{(float*)T.qf, (float*)T.Ws, (float*)T.gW, (float*)T.gf, (float*)T.PhiA, (float*)T.Phi};
+    else
+      L->w64 = T;
+  }
 
   LevelDev& D = L->dev;
   memset(&D, 0, sizeof(D));
@@ -1250,7 +1261,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   const double w = prec == PREC_F32 ? 4.0 : 8.0;
   double b = 4.0 * (3 * K + (K + 1) + 6 * K + c.nn + c.nm + c.nm / 64.0 + 2) + sizeof(FaceRec) * c.nfaces;
   b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));  // FP64 geometry
-  b += w * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf + 5 * c.nf);  // work arrays
+  if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf + 5 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 4.0 * K + 16.0 * c.ntiles;                  // element tiles
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
