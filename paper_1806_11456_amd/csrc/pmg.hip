@@ -130,7 +130,7 @@ enum { PREC_F64 = 0, PREC_F32 = 1 };
 // Work arrays of the operator stages in a level's precision.
 template <class T>
 struct Work {
-  T *qf = nullptr, *Ws = nullptr, *gW = nullptr, *gf = nullptr, *PhiA = nullptr, *Phi = nullptr;
+  T *qf = nullptr, *Ws = nullptr, *gW = nullptr, *gf = nullptr, *Phi = nullptr;
 };
 
 struct Level {
@@ -277,6 +277,11 @@ struct pmg_solver_s {
   int* d_act[2] = {nullptr, nullptr};        // per problem: the problems a batched cycle advances
   std::unique_ptr<Hier> iso64;               // FP64 isotropic hierarchy of a mixed-precision solver
   std::vector<int> fp32_cycles;              // per problem: cycles of the last solve with FP32 coarse levels
+  // the shared face-trace array holds the traces of this state on this level (launch-order bookkeeping:
+  // k_trace is skipped when the next evaluation is of the same state on the same level)
+  mutable const Level* qf_level = nullptr;
+  mutable const void* qf_src = nullptr;
+  mutable const int* qf_act = nullptr;  // the active-problem array of that evaluation (nullptr: all problems)
   std::vector<int> iso_caps;                 // order caps of the isotropic levels, finest first
   double* d_taumap = nullptr;                // scratch tau map of pmg_tau_nodal
   std::vector<double> history;               // residual checks of the last pmg_solve
@@ -450,13 +455,12 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
     W.Ws = A.alloc<double>(4 * nf);
     W.gW = A.alloc<double>(12 * nn);
     W.gf = A.alloc<double>(12 * nf);
-    W.PhiA = A.alloc<double>(5 * nf);
     W.Phi = A.alloc<double>(5 * nf);
   } else {
     const Work<double>& T = s->top->w64;
     REQUIRE(nn <= s->top->nn && nf <= s->top->nf, "coarse level larger than the finest");
     if (prec == PREC_F32)
-      L->w32 = Work<float>{(float*)T.qf, (float*)T.Ws, (float*)T.gW, (float*)T.gf, (float*)T.PhiA, (float*)T.Phi};
+      L->w32 = Work<float>{(float*)T.qf, (float*)T.Ws, (float*)T.gW, (float*)T.gf, (float*)T.Phi};
     else
       L->w64 = T;
   }
@@ -562,31 +566,45 @@ static DivArgs<T> div_args(int mode) {
 // numerical flux, divergence (the epilogue in 'a' decides what is written).  T is the level's precision.
 // 'act' (nullable): the problems advanced by a cycle; tiles of the others return at once and leave their
 // outputs untouched (a frozen problem's state and correction stay exactly as they are).
+// The shared trace array no longer describes any state (called whenever a state or the array may change
+// outside op_eval: transfers, copies, graph replays, every entry point).
+static void traces_stale(const pmg_solver_s* s) {
+  s->qf_level = nullptr;
+  s->qf_src = nullptr;
+  s->qf_act = nullptr;
+}
+
 template <class T>
-static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, const DivArgs<T>& a,
+static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, const DivArgs<T>& a_in,
                     hipStream_t st, const int* act = nullptr) {
   LevelDevT<T> D = L.devT<T>();
   if (act) D.active = D.skip = act;
   const Work<T>& W = L.work<T>();
   const double nn = L.nn, nf = L.nf, nm = L.nm, w = sizeof(T);
-  PROF_LAUNCH(s, PK_TRACE, st, (5 * nn + 5 * nf) * w,
-              k_trace<T><<<L.ntiles, PMG_BLOCK, L.lds_trace(), st>>>(D, Q, W.qf));
+  DivArgs<T> a = a_in;
+  if (a.mode == EPI_RK) a.qf_out = W.qf;  // the stage leaves the traces of the state it writes
+  // traces written for every problem serve any later evaluation; traces written with frozen problems
+  // skipped serve only evaluations over the same problems
+  const bool fresh = s->qf_level == &L && s->qf_src == (const void*)Q && (s->qf_act == nullptr || s->qf_act == act);
+  if (!fresh)
+    PROF_LAUNCH(s, PK_TRACE, st, (5 * nn + 5 * nf) * w,
+                k_trace<T><<<L.ntiles, PMG_BLOCK, L.lds_trace(), st>>>(D, Q, W.qf));
   if (isolated)
-    PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 3 * nf + 4 * nf + 5 * nf) * w,
-                k_face1_iso<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, W.qf, W.Ws, W.Phi));
+    PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nf) * w,
+                k_face1_iso<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, W.qf, W.Ws));
   else
-    PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nm + 4 * nf + 5 * nf) * w,
-                k_face1<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.Ws, W.PhiA));
+    PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nf) * w,
+                k_face1<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.Ws));
   const bool one = L.max_tile <= PMG_BLOCK;  // one node per thread in every tile
   PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn + 12 * nf) * w,
               (one ? k_grad<T, 1> : k_grad<T, PMG_NPT>)<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(
                   D, Q, W.Ws, W.gW, W.gf));
   if (isolated)
-    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 2 * 4 * nf) * w,
+    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 5 * nf) * w,
                 k_face2_iso<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, W.qf, W.gf, W.Phi));
   else
-    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 4 * nm + 5 * nf + 5 * nf) * w,
-                k_face2<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.gf, W.PhiA, W.Phi));
+    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 4 * nm + 5 * nf) * w,
+                k_face2<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.gf, W.Phi));
   // divergence: Q, grad W, J a, 1/J, Phi in; the epilogue's own arrays
   double epi = 0.0;
   switch (a.mode) {
@@ -596,9 +614,13 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
     case EPI_TAU: epi = a.Sphys ? 5 * nn : 0; break;
     default: epi = 5 * nn;
   }
+  if (a.mode == EPI_RK) epi += 5 * nf;  // the fused traces
   PROF_LAUNCH(s, PK_DIV, st, (27 * nn + 5 * nf + epi) * w,
               (one ? k_div<T, 1> : k_div<T, PMG_NPT>)<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(
                   D, Q, W.gW, W.Phi, a));
+  s->qf_level = &L;
+  s->qf_src = a.mode == EPI_RK ? (const void*)a.Qrk : (const void*)Q;
+  s->qf_act = fresh && s->qf_act == nullptr ? nullptr : act;
 }
 
 static const double RK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
@@ -686,6 +708,7 @@ static void residual_any(const pmg_solver_s* s, Level& L, const void* Q, const v
 template <class TU, class TV>
 static void xfer_t(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
                    const TU* U, const TU* U0, TV* V, bool accumulate, hipStream_t st) {
+  traces_stale(s);  // V may be a state whose traces are held
   XferArgs<TU, TV> a;
   a.tiles = prolong ? X.d_prolong : X.d_restrict;
   a.elist = X.d_elist;
@@ -749,6 +772,7 @@ static std::string level_key(const pmg_solver_s* s, const Level& L) {
 }
 
 static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
+  traces_stale(s);
   std::string key = level_key(s, L);
   auto it = s->ctx->tile_cache.find(key);
   if (it != s->ctx->tile_cache.end()) {
@@ -784,6 +808,7 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
   s->prof->mask = mask;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  traces_stale(s);  // the timing state is freed
   if (best != L.tile_target) build_tiles(s, L, best);
   s->ctx->tile_cache[key] = best;
 }
@@ -983,6 +1008,7 @@ static void set_sources(CycleCtx& c, const double* S) {
 
 static void run_vcycles(pmg_solver_s* s, Hier& H, double* Q, const double* S, int ncycles, const TauRec* tau,
                         hipStream_t st, const int* act = nullptr) {
+  traces_stale(s);
   CycleCtx c{s, &H, st, tau, act};
   int top = H.top();
   H.Q[top] = Q;
@@ -1052,6 +1078,7 @@ static void run_graph(pmg_solver_s* s, const GraphKey& key, int repeats, hipStre
     it = s->graphs.emplace(key, ex).first;
   }
   for (int r = 0; r < repeats; r++) HIPCHECK(hipGraphLaunch(it->second, st));
+  traces_stale(s);  // the replay rewrote the trace array
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1261,7 +1288,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   const double w = prec == PREC_F32 ? 4.0 : 8.0;
   double b = 4.0 * (3 * K + (K + 1) + 6 * K + c.nn + c.nm + c.nm / 64.0 + 2) + sizeof(FaceRec) * c.nfaces;
   b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));  // FP64 geometry
-  if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf + 5 * c.nf);  // shared work arrays
+  if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 4.0 * K + 16.0 * c.ntiles;                  // element tiles
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
@@ -1412,6 +1439,7 @@ pmg_status pmg_batch_layout(pmg_solver s, int* n_problems, int64_t* problem_node
 pmg_status pmg_init_freestream(pmg_solver s, double* Q_dev, void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev, "NULL argument");
+    traces_stale(s);
     k_freestream<<<cdiv(s->top->nn, 256), 256, 0, (hipStream_t)stream>>>(s->top->dev, Q_dev);
     HIPCHECK(hipGetLastError());
   });
@@ -1421,6 +1449,7 @@ pmg_status pmg_residual(pmg_solver s, int op, const double* Q_dev, const double*
                         double* res_inf_host, void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && R_dev, "NULL argument");
+    traces_stale(s);
     REQUIRE(op == 0 || op == 1, "op must be 0 (DG) or 1 (isolated)");
     hipStream_t st = (hipStream_t)stream;
     residual(s, *s->top, Q_dev, S_dev, R_dev, op == 1, res_inf_host ? SLOT_NORM : -1, st);
@@ -1436,6 +1465,7 @@ pmg_status pmg_batch_norms(pmg_solver s, const double* Q_dev, const double* S_de
                            void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && res_inf_host, "NULL argument");
+    traces_stale(s);
     hipStream_t st = (hipStream_t)stream;
     residual(s, *s->top, Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
     std::vector<double> v = read_slots(s, SLOT_NORM, st);
@@ -1458,6 +1488,7 @@ pmg_status pmg_timestep(pmg_solver s, const double* Q_dev, double* dt_host, void
 pmg_status pmg_smooth(pmg_solver s, double* Q_dev, const double* S_dev, int sweeps, void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && sweeps >= 0, "bad argument");
+    traces_stale(s);
     smooth(s, *s->top, Q_dev, S_dev, s->d_G, sweeps, (hipStream_t)stream);
     HIPCHECK(hipGetLastError());
   });
@@ -1484,6 +1515,7 @@ pmg_status pmg_level_info(pmg_solver s, int hierarchy, int level, int32_t* n_lev
 pmg_status pmg_restrict(pmg_solver s, int hierarchy, int level, const double* Uf, double* Uc, void* stream) {
   return guard([&] {
     REQUIRE(s && Uf && Uc, "NULL argument");
+    traces_stale(s);
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 1 && level < (int)H.lv.size(), "level out of range");
     xfer64(s, *H.lv[level], *H.lv[level - 1], *H.xf[level - 1], false, Uf, Uc, (hipStream_t)stream);
@@ -1494,6 +1526,7 @@ pmg_status pmg_restrict(pmg_solver s, int hierarchy, int level, const double* Uf
 pmg_status pmg_prolong(pmg_solver s, int hierarchy, int level, const double* Uc, double* Uf, void* stream) {
   return guard([&] {
     REQUIRE(s && Uf && Uc, "NULL argument");
+    traces_stale(s);
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 0 && level + 1 < (int)H.lv.size(), "level out of range");
     xfer64(s, *H.lv[level], *H.lv[level + 1], *H.xf[level], true, Uc, Uf, (hipStream_t)stream);
@@ -1511,6 +1544,7 @@ pmg_status pmg_set_graph(pmg_solver s, int enable) {
 pmg_status pmg_autotune(pmg_solver s, void* stream) {
   return guard([&] {
     REQUIRE(s, "NULL solver");
+    traces_stale(s);
     hipStream_t st = (hipStream_t)stream;
     std::vector<Level*> done;
     auto tune = [&](Hier& H) {
@@ -1543,6 +1577,7 @@ pmg_status pmg_vcycle(pmg_solver s, double* Q_dev, const double* S_dev, int n_cy
                       void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && n_cycles >= 0, "bad argument");
+    traces_stale(s);
     hipStream_t st = (hipStream_t)stream;
     if (s->use_graph && !s->mg.tuning && n_cycles > 0) {
       // sources once eagerly, then the captured cycle (its sources are re-derived inside; identical work)
@@ -1706,6 +1741,8 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
 pmg_status pmg_solve_stats(pmg_solver s, int32_t* fp32_cycles) {
   return guard([&] {
     REQUIRE(s && fp32_cycles, "NULL argument");
+    traces_stale(s);
+    traces_stale(s);
     for (int p = 0; p < s->nprob; p++) fp32_cycles[p] = s->fp32_cycles[p];
   });
 }
@@ -2000,6 +2037,7 @@ pmg_status pmg_tau_estimate(pmg_solver s, double* Q_dev, const double* S_dev, in
                             void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && tau_map_dev, "NULL argument");
+    traces_stale(s);
     hipStream_t st = (hipStream_t)stream;
     const int nt = std::max(s->nmax - 1, 1);
     TauRec tau{tau_map_dev, nt, isolated ? 1 : 0};
@@ -2073,6 +2111,7 @@ pmg_status pmg_checkpoint(pmg_solver s, const char* path, const double* Q_dev, v
 pmg_status pmg_restore(pmg_solver s, const char* path, double* Q_dev, void* stream) {
   return guard([&] {
     REQUIRE(s && path && Q_dev, "NULL argument");
+    traces_stale(s);
     FILE* f = fopen(path, "rb");
     REQUIRE(f, std::string("cannot open ") + path);
     std::vector<unsigned char> buf;
@@ -2129,6 +2168,7 @@ pmg_status pmg_tau_nodal(pmg_solver s, int dir, int order, double* Q_dev, const 
                          double* tau_dev, void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && tau_dev, "NULL argument");
+    traces_stale(s);
     REQUIRE(dir >= 0 && dir <= 2, "dir must be 0, 1 or 2");
     Hier& H = aniso_hier(s, dir);
     int lev = -1;
