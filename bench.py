@@ -199,6 +199,11 @@ def main() -> int:
     tau_dirs = sum(1 for d in range(3) if int(wl.orders[:, d].max()) > 1)
     evals_per_step = per_cycle * (1 + tau_dirs)
 
+    # one step builds every level (the anisotropic hierarchies on first use); the tile autotuner then picks
+    # each level's element-tile size
+    step()
+    torch.cuda.synchronize()
+    s.autotune()
     # warm-up; the first step times every kernel kind to find the dominant one
     s.profile(KINDS)
     step()
@@ -256,6 +261,7 @@ def main() -> int:
                         "N=(6,6,1) Gauss, Mach 0.2, Re_L 1e5, wall + far field",
             "dof": dof,
             "step": f"isotropic FAS V-cycle (levels 6..1, beta {b1}/{b2}/{bc}) + anisotropic 3V isolated tau",
+            "tiles": "autotuned per level",
             "fine_residual_evals_per_step": evals_per_step,
         },
         "roofline": {

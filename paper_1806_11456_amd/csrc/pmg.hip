@@ -144,6 +144,7 @@ struct Level {
   int4* d_tiles;
   FaceRec* d_faces;
   double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;  // geometry in FP64 (always kept)
+  double* d_hfac = nullptr;                        // [2][nn] geometric factors of the CFL step
   Work<double> w64;
   Work<float> w32;
   LevelDevT<double> dev;
@@ -159,7 +160,8 @@ struct Level {
   size_t wsize() const { return prec == PREC_F32 ? sizeof(float) : sizeof(double); }
   size_t lds_trace() const { return (size_t)5 * max_tile * wsize(); }
   size_t lds_grad() const { return (size_t)13 * max_tile * wsize(); }
-  size_t lds_div() const { return (size_t)15 * max_tile * wsize(); }
+  // flux rows, plus the updated-state rows of an RK stage when one node per thread (tiles <= PMG_BLOCK)
+  size_t lds_div() const { return (size_t)(max_tile <= PMG_BLOCK ? 20 : 15) * max_tile * wsize(); }
 };
 
 struct XferTiles {
@@ -492,6 +494,8 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   k_geo_metric<<<nb, 256>>>(D, G);
   k_geo_faces<<<L->ntiles, PMG_BLOCK>>>(D, L->d_Nout);
   if (L->nm > 0) k_mortar_geo<<<cdiv(L->nm, 256), 256>>>(D, L->d_mgeo);
+  L->d_hfac = A.alloc<double>(2 * nn);
+  k_hfac<<<nb, 256>>>(D, L->d_hfac);
   if (prec == PREC_F32) {
     // FP32 copies of the metric terms, each rounded once from the FP64 geometry
     LevelDevT<float>& F = L->dev32;
@@ -655,8 +659,8 @@ static void timestep(const pmg_solver_s* s, Level& L, const T* Q, hipStream_t st
   reset_slot(s, SLOT_DT, INFINITY, st);
   LevelDevT<T> D = L.devT<T>();
   if (act) D.active = D.skip = act;
-  PROF_LAUNCH(s, PK_DT, st, 15.0 * L.nn * sizeof(T),
-              k_dt<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, slot_ptr(s, SLOT_DT)));
+  PROF_LAUNCH(s, PK_DT, st, L.nn * (5.0 * sizeof(T) + 16.0),
+              k_dt<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, L.d_hfac, slot_ptr(s, SLOT_DT)));
 }
 
 template <class T>
@@ -1287,7 +1291,7 @@ static LevelCount count_level(const pmg_mesh_s* m, const std::vector<int>& ord, 
 static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   const double w = prec == PREC_F32 ? 4.0 : 8.0;
   double b = 4.0 * (3 * K + (K + 1) + 6 * K + c.nn + c.nm + c.nm / 64.0 + 2) + sizeof(FaceRec) * c.nfaces;
-  b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));  // FP64 geometry
+  b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0) + 2 * c.nn);  // FP64 geometry
   if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 4.0 * K + 16.0 * c.ntiles;                  // element tiles
