@@ -139,6 +139,67 @@ def serve_bench(args) -> dict:
     }
 
 
+def solve_bench(args) -> dict:
+    """Time to a converged solve: the flat plate from the far-field state to ||r||_inf < tol with FP64 FAS
+    V-cycles (beta 2/2/4, captured graphs), the norm read every 'chunk' cycles; the oracle's time is
+    extrapolated as (cycles) x (one oracle V-cycle on the same plate, measured)."""
+    import torch
+
+    from paper_1806_11456_amd import inputs as I
+    from paper_1806_11456_amd import pmg
+
+    wl = I.config_plate()
+    ctx = pmg.Context(0)
+    mg = pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4, precision=args.solve_precision)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys, mg)
+    s.set_graph(True)
+    Q = s.freestream()
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t_setup
+    r0 = s.residual(Q, None, norm=True)[1]
+    chunk = args.solve_chunk
+    cycles, r = 0, r0
+    hist = [(0, r0)]
+    t0 = time.perf_counter()
+    while r >= args.solve_tol and cycles < args.solve_max_cycles and time.perf_counter() - t0 < args.solve_max_s:
+        if args.solve_precision == 1:
+            # mixed precision: the solver's own precision switch decides per cycle
+            c, r = s.solve(Q, None, tol=args.solve_tol, max_cycles=chunk, raise_not_converged=False)
+        else:
+            r = s.vcycle(Q, None, n_cycles=chunk, norm=True)
+            c = chunk
+        cycles += c
+        hist.append((cycles, r))
+        print(f"solve: {cycles} cycles, residual {r:.3e}, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"metric": "time to converged solve", "value": wall if r < args.solve_tol else None, "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f64" if args.solve_precision == 0 else "mixed f32/f64",
+           "data": "synthetic",
+           "config": {"workload": "flat-plate boundary layer: 64x32x1 stretched hexes (ratio 1.1), quadratic "
+                                  "mapping, N=(6,6,1) Gauss, Mach 0.2, Re_L 1e5, wall + far field; far-field start",
+                      "dof": s.n_nodes, "tol": args.solve_tol, "vcycle": "levels 6..1, beta 2/2/4, graph replay",
+                      "norm_every": chunk},
+           "converged": bool(r < args.solve_tol), "cycles": cycles, "wall_s": wall, "residual": r,
+           "initial_residual": r0, "setup_s": setup, "ms_per_cycle": 1e3 * wall / max(cycles, 1),
+           "history": hist}
+    if not args.no_cpu:
+        from oracle import oracle as O
+        o = O.Oracle(wl.mesh, wl.phys)
+        Qf = I.freestream_state(wl.n_nodes, wl.phys.mach)
+        c0 = time.perf_counter()
+        o.vcycles(wl.orders, Qf, None, ncycles=1, beta_pre=2, beta_post=2, beta_coarse=4)
+        oc = time.perf_counter() - c0
+        out["cpu_baseline"] = {"kind": "oracle", "cores": 1, "oracle_s_per_cycle": oc,
+                               "extrapolated_s": oc * cycles,
+                               "sample": "one oracle V-cycle on the same plate state (FP64 C oracle, one thread); "
+                                         "time to solve = cycles x that, extrapolated"}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +218,12 @@ def main() -> int:
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-precision", type=int, default=0)
+    ap.add_argument("--solve", action="store_true", help="time to a converged plate solve instead of throughput")
+    ap.add_argument("--solve-tol", type=float, default=1e-9)
+    ap.add_argument("--solve-chunk", type=int, default=2000)
+    ap.add_argument("--solve-max-cycles", type=int, default=400000)
+    ap.add_argument("--solve-max-s", type=float, default=1000.0)
+    ap.add_argument("--solve-precision", type=int, default=0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -167,6 +234,9 @@ def main() -> int:
 
     if args.serve:
         print(json.dumps(serve_bench(args)), flush=True)
+        return 0
+    if args.solve:
+        print(json.dumps(solve_bench(args)), flush=True)
         return 0
 
     import numpy as np

@@ -138,6 +138,7 @@ struct Level {
   int prec = PREC_F64;  // working precision of the operator and smoother on this level
   std::vector<int> ord, off, fo;
   int ntiles = 0, nftiles = 0, max_tile = 0, tile_target = 256;
+  int block = PMG_BLOCK;  // threads per element tile: the smallest of 64, 128, 256 that holds the largest tile
   DevArena arena;
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile;
@@ -160,8 +161,8 @@ struct Level {
   size_t wsize() const { return prec == PREC_F32 ? sizeof(float) : sizeof(double); }
   size_t lds_trace() const { return (size_t)5 * max_tile * wsize(); }
   size_t lds_grad() const { return (size_t)13 * max_tile * wsize(); }
-  // flux rows, plus the updated-state rows of an RK stage when one node per thread (tiles <= PMG_BLOCK)
-  size_t lds_div() const { return (size_t)(max_tile <= PMG_BLOCK ? 20 : 15) * max_tile * wsize(); }
+  // flux rows, plus the updated-state rows of an RK stage when one node per thread (tiles <= block)
+  size_t lds_div() const { return (size_t)(max_tile <= block ? 20 : 15) * max_tile * wsize(); }
 };
 
 struct XferTiles {
@@ -340,6 +341,7 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   L.ntiles = (int)tiles.size();
   L.max_tile = max_tile;
   L.tile_target = target;
+  L.block = max_tile <= 64 ? 64 : (max_tile <= 128 ? 128 : PMG_BLOCK);
   L.dev.tiles = L.dev32.tiles = L.d_tiles;
   L.dev.elist = L.dev32.elist = L.d_elist;
 }
@@ -566,6 +568,58 @@ static DivArgs<T> div_args(int mode) {
   return a;
 }
 
+// Element-tile launches: the kernel instance whose block size is the level's (and, for the gradient and the
+// divergence, one node per thread unless a tile is larger than the block).
+template <class T>
+static void launch_trace(const Level& L, const LevelDevT<T>& D, const T* Q, T* qf, hipStream_t st) {
+  const size_t lds = L.lds_trace();
+  if (L.block == 64) k_trace<T, 64><<<L.ntiles, 64, lds, st>>>(D, Q, qf);
+  else if (L.block == 128) k_trace<T, 128><<<L.ntiles, 128, lds, st>>>(D, Q, qf);
+  else k_trace<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf);
+}
+
+template <class T>
+static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const T* Ws, T* gW, T* gf,
+                        hipStream_t st) {
+  const size_t lds = L.lds_grad();
+  if (L.block == 64) k_grad<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, Ws, gW, gf);
+  else if (L.block == 128) k_grad<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, Ws, gW, gf);
+  else if (L.max_tile <= PMG_BLOCK) k_grad<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, Ws, gW, gf);
+  else k_grad<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, Ws, gW, gf);
+}
+
+template <class T>
+static void launch_div(const Level& L, const LevelDevT<T>& D, const T* Q, const T* gW, const T* Phi,
+                       const DivArgs<T>& a, hipStream_t st) {
+  const size_t lds = L.lds_div();
+  if (L.block == 64) k_div<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, gW, Phi, a);
+  else if (L.block == 128) k_div<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, gW, Phi, a);
+  else if (L.max_tile <= PMG_BLOCK) k_div<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, gW, Phi, a);
+  else k_div<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, gW, Phi, a);
+}
+
+template <class T>
+static void launch_face1_iso(const Level& L, const LevelDevT<T>& D, const T* qf, T* Ws, hipStream_t st) {
+  if (L.block == 64) k_face1_iso<T, 64><<<L.ntiles, 64, 0, st>>>(D, qf, Ws);
+  else if (L.block == 128) k_face1_iso<T, 128><<<L.ntiles, 128, 0, st>>>(D, qf, Ws);
+  else k_face1_iso<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, qf, Ws);
+}
+
+template <class T>
+static void launch_face2_iso(const Level& L, const LevelDevT<T>& D, const T* qf, const T* gf, T* Phi,
+                             hipStream_t st) {
+  if (L.block == 64) k_face2_iso<T, 64><<<L.ntiles, 64, 0, st>>>(D, qf, gf, Phi);
+  else if (L.block == 128) k_face2_iso<T, 128><<<L.ntiles, 128, 0, st>>>(D, qf, gf, Phi);
+  else k_face2_iso<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, qf, gf, Phi);
+}
+
+template <class T>
+static void launch_dt(const Level& L, const LevelDevT<T>& D, const T* Q, unsigned long long* out, hipStream_t st) {
+  if (L.block == 64) k_dt<T, 64><<<L.ntiles, 64, 0, st>>>(D, Q, L.d_hfac, out);
+  else if (L.block == 128) k_dt<T, 128><<<L.ntiles, 128, 0, st>>>(D, Q, L.d_hfac, out);
+  else k_dt<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, L.d_hfac, out);
+}
+
 // A(Q) through the stages: q traces, interface state + Roe flux, gradient (+ gradient traces), viscous
 // numerical flux, divergence (the epilogue in 'a' decides what is written).  T is the level's precision.
 // 'act' (nullable): the problems advanced by a cycle; tiles of the others return at once and leave their
@@ -592,20 +646,18 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
   const bool fresh = s->qf_level == &L && s->qf_src == (const void*)Q && (s->qf_act == nullptr || s->qf_act == act);
   if (!fresh)
     PROF_LAUNCH(s, PK_TRACE, st, (5 * nn + 5 * nf) * w,
-                k_trace<T><<<L.ntiles, PMG_BLOCK, L.lds_trace(), st>>>(D, Q, W.qf));
+                launch_trace(L, D, Q, W.qf, st));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nf) * w,
-                k_face1_iso<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, W.qf, W.Ws));
+                launch_face1_iso(L, D, (const T*)W.qf, W.Ws, st));
   else
     PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nf) * w,
                 k_face1<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.Ws));
-  const bool one = L.max_tile <= PMG_BLOCK;  // one node per thread in every tile
   PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn + 12 * nf) * w,
-              (one ? k_grad<T, 1> : k_grad<T, PMG_NPT>)<<<L.ntiles, PMG_BLOCK, L.lds_grad(), st>>>(
-                  D, Q, W.Ws, W.gW, W.gf));
+              launch_grad(L, D, Q, (const T*)W.Ws, W.gW, W.gf, st));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 5 * nf) * w,
-                k_face2_iso<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, W.qf, W.gf, W.Phi));
+                launch_face2_iso(L, D, (const T*)W.qf, (const T*)W.gf, W.Phi, st));
   else
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 4 * nm + 5 * nf) * w,
                 k_face2<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.gf, W.Phi));
@@ -620,8 +672,7 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
   }
   if (a.mode == EPI_RK) epi += 5 * nf;  // the fused traces
   PROF_LAUNCH(s, PK_DIV, st, (27 * nn + 5 * nf + epi) * w,
-              (one ? k_div<T, 1> : k_div<T, PMG_NPT>)<<<L.ntiles, PMG_BLOCK, L.lds_div(), st>>>(
-                  D, Q, W.gW, W.Phi, a));
+              launch_div(L, D, Q, (const T*)W.gW, (const T*)W.Phi, a, st));
   s->qf_level = &L;
   s->qf_src = a.mode == EPI_RK ? (const void*)a.Qrk : (const void*)Q;
   s->qf_act = fresh && s->qf_act == nullptr ? nullptr : act;
@@ -660,7 +711,7 @@ static void timestep(const pmg_solver_s* s, Level& L, const T* Q, hipStream_t st
   LevelDevT<T> D = L.devT<T>();
   if (act) D.active = D.skip = act;
   PROF_LAUNCH(s, PK_DT, st, L.nn * (5.0 * sizeof(T) + 16.0),
-              k_dt<T><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, L.d_hfac, slot_ptr(s, SLOT_DT)));
+              launch_dt(L, D, Q, slot_ptr(s, SLOT_DT), st));
 }
 
 template <class T>
