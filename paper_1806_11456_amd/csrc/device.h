@@ -70,9 +70,13 @@ struct LevelDevT {
   const T* __restrict__ Nout;         // [3][nf] outward normal x surface Jacobian, own side
   const int4* __restrict__ tiles;     // {first, count, packed n1|n2<<8|n3<<16, nodes}
   const int* __restrict__ elist;
+  const int* __restrict__ tprob;      // problem of each tile
+  const int* __restrict__ eoff;       // per elist entry: first node of the element (off[elist[k]])
+  const int* __restrict__ efo;        // per elist entry: first face node of the element (fo[6 elist[k]])
   const FaceRec* __restrict__ faces;
   const int* __restrict__ mface;      // mortar node -> face
   const int* __restrict__ ftile;      // face tile boundaries in mortar nodes
+  const int* __restrict__ ftprob;     // problem of each face tile
   const T* __restrict__ mgeo;         // [4][nm] unit normal (master outward) and surface Jacobian
   const double* __restrict__ T_;      // transfer tables of this family
 };

@@ -141,7 +141,8 @@ struct Level {
   int block = PMG_BLOCK;  // threads per element tile: the smallest of 64, 128, 256 that holds the largest tile
   DevArena arena;
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
-  int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile;
+  int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile, *d_ftprob;
+  int *d_tprob = nullptr, *d_eoff = nullptr, *d_efo = nullptr;  // per tile / per elist entry
   int4* d_tiles;
   FaceRec* d_faces;
   double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;  // geometry in FP64 (always kept)
@@ -334,16 +335,28 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
     }
   }
   REQUIRE(max_tile <= PMG_TILE_MAX, "element tile too large");
+  std::vector<int> tprob(tiles.size()), eoff(elist.size()), efo(elist.size());
+  for (size_t t = 0; t < tiles.size(); t++) tprob[t] = s->eprob[elist[tiles[t].x]];
+  for (size_t k = 0; k < elist.size(); k++) {
+    eoff[k] = L.off[elist[k]];
+    efo[k] = L.fo[6 * elist[k]];
+  }
   L.tile_arena.~DevArena();
   new (&L.tile_arena) DevArena();
   L.d_elist = L.tile_arena.upload(elist);
   L.d_tiles = L.tile_arena.upload(tiles);
+  L.d_tprob = L.tile_arena.upload(tprob);
+  L.d_eoff = L.tile_arena.upload(eoff);
+  L.d_efo = L.tile_arena.upload(efo);
   L.ntiles = (int)tiles.size();
   L.max_tile = max_tile;
   L.tile_target = target;
   L.block = max_tile <= 64 ? 64 : (max_tile <= 128 ? 128 : PMG_BLOCK);
   L.dev.tiles = L.dev32.tiles = L.d_tiles;
   L.dev.elist = L.dev32.elist = L.d_elist;
+  L.dev.tprob = L.dev32.tprob = L.d_tprob;
+  L.dev.eoff = L.dev32.eoff = L.d_eoff;
+  L.dev.efo = L.dev32.efo = L.d_efo;
 }
 
 static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int>& ord, int prec = PREC_F64) {
@@ -429,6 +442,8 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   }
   if (ftile.back() != (int)mface.size()) ftile.push_back((int)mface.size());
   L->nftiles = (int)ftile.size() - 1;
+  std::vector<int> ftprob(std::max(L->nftiles, 1), 0);
+  for (int t = 0; t < L->nftiles; t++) ftprob[t] = s->eprob[faces[mface[ftile[t]]].eM];
   L->nm = (int)mface.size();
 
   std::vector<int> node_elem(nn);
@@ -443,6 +458,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_faces = A.upload(faces);
   L->d_mface = A.upload(mface);
   L->d_ftile = A.upload(ftile);
+  L->d_ftprob = A.upload(ftprob);
   L->d_Ja = A.alloc<double>(9 * nn);
   L->d_invJ = A.alloc<double>(nn);
   L->d_J = A.alloc<double>(nn);
@@ -477,7 +493,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   D.active = s->d_ones;
   D.ord = L->d_ord; D.off = L->d_off; D.fo = L->d_fo;
   D.Ja = L->d_Ja; D.invJ = L->d_invJ; D.J = L->d_J; D.Nout = L->d_Nout;
-  D.faces = L->d_faces; D.mface = L->d_mface; D.ftile = L->d_ftile; D.mgeo = L->d_mgeo;
+  D.faces = L->d_faces; D.mface = L->d_mface; D.ftile = L->d_ftile; D.ftprob = L->d_ftprob; D.mgeo = L->d_mgeo;
   D.T_ = s->ctx->T[L->fam];
   build_tiles(s, *L, 256);
 
@@ -505,8 +521,9 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
     F.K = D.K; F.nn = D.nn; F.nf = D.nf; F.nm = D.nm; F.fam = D.fam;
     F.ptab = D.ptab; F.eprob = D.eprob; F.node_elem = D.node_elem; F.dt = D.dt; F.active = D.active;
     F.ord = D.ord; F.off = D.off; F.fo = D.fo; F.faces = D.faces; F.mface = D.mface; F.ftile = D.ftile;
+    F.ftprob = D.ftprob;
     F.T_ = D.T_;
-    F.tiles = D.tiles; F.elist = D.elist;
+    F.tiles = D.tiles; F.elist = D.elist; F.tprob = D.tprob; F.eoff = D.eoff; F.efo = D.efo;
     auto down = [&](const double* src, size_t n) {
       float* dst = A.alloc<float>(n);
       k_copy<<<cdiv(n, 256), 256>>>(dst, src, n);
@@ -1345,7 +1362,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0) + 2 * c.nn);  // FP64 geometry
   if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
-  b += 4.0 * K + 16.0 * c.ntiles;                  // element tiles
+  b += 3 * 4.0 * K + 20.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
   b += 4.0 * K + 2 * 16.0 * K;                     // transfer tiles towards this level (upper bound)
   return b;
