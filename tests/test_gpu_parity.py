@@ -59,11 +59,14 @@ def test_timestep(ctx, pairs, name):
 
 
 def state_tol(o, wl, n_evals):
-    """Bar for a state after n_evals RK stage evaluations: every stage adds b dt r, and r carries the
-    residual bar 1e-12 x (its round-off scale); relative to |Q| that is 1e-12 x dt x scale / |Q| per stage."""
+    """Bar for a state after n_evals operator evaluations: every stage adds b dt r, and r carries the
+    residual bar 1e-12 x (its round-off scale); relative to |Q_v| that is 1e-12 x dt x scale_v / |Q_v| per
+    evaluation, for every variable (the momentum components share one |Q|, as in check())."""
     _, sc = o.operator_scale(wl.orders, wl.Q)
     dt = o.timestep(wl.orders, wl.Q)
-    ratio = max((dt * sc[v].max()) / np.abs(wl.Q[v]).max() for v in (0, 4))
+    qmax = np.abs(wl.Q).max(axis=1)
+    qmax[1:4] = qmax[1:4].max()
+    ratio = max((dt * sc[v].max()) / qmax[v] for v in range(5))
     return 1e-12 * max(1.0, n_evals * ratio)
 
 
@@ -170,3 +173,33 @@ def test_full_size_residual(ctx, which):
         Rg = np_(s.residual(s.tensor(wl.Q), None, isolated=iso))
         A, scale = o.operator_scale(wl.orders, wl.Q, isolated=iso)
         check(Rg, -A, scale, 1e-12, f"{which} full-size iso={iso}")
+
+
+def test_full_size_bench_step(ctx):
+    """The timed bench step at full size and in its launch configuration (autotuned tiles): one isotropic
+    V-cycle (levels 6..1, beta 2/2/4) then the isolated 3V truncation-error estimate, on the 64x32x1 plate,
+    against the oracle's V-cycle and 3V cycle on the same state."""
+    from oracle import oracle as O
+    from paper_1806_11456_amd import pmg
+    wl = I.config_plate()
+    mg = dict(beta_pre=2, beta_post=2, beta_coarse=4)
+    s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys, pmg.MG(**mg))
+    Q = s.tensor(wl.Q)
+    s.tau_estimate(s.tensor(wl.Q), None, isolated=True)  # builds every level, as the bench's first step
+    s.autotune()
+    s.vcycle(Q, None, n_cycles=1)
+    tau = np_(s.tau_estimate(Q, None, isolated=True))
+    o = O.Oracle(wl.mesh, wl.phys)
+    Qo, _ = o.vcycles(wl.orders, wl.Q, None, ncycles=1, **mg)
+    to, Qo = o.tau_3v(wl.orders, Qo, None, isolated=1, **mg)
+    # every operator evaluation of the step adds at most the residual bar times its step: per cycle 13 on the
+    # finest level (12 RK stages + the restricted residual), 14 on each of the 4 intermediate levels (FAS
+    # source, 12 stages, residual), 13 on the coarsest (source, 12 stages); three cycles (isotropic, x, y)
+    # plus the 2 x 5 isolated tau evaluations = 256; x 2 for the max-norm growth of an explicit stage map
+    n_evals = 3 * (13 + 4 * 14 + 13) + 2 * 5
+    stol = state_tol(o, wl, 2 * n_evals)
+    check(np_(Q), Qo, None, stol, "bench step state")
+    assert np.array_equal(np.isnan(tau), np.isnan(to))
+    m = ~np.isnan(to)
+    _, sc = o.operator_scale(wl.orders, wl.Q)
+    assert np.abs(tau[m] - to[m]).max() <= (1e-12 + stol) * sc.max()
