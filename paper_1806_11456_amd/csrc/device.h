@@ -78,8 +78,13 @@ struct LevelDevT {
   const int* __restrict__ ftile;      // face tile boundaries in mortar nodes
   const int* __restrict__ ftprob;     // problem of each face tile
   const T* __restrict__ mgeo;         // [4][nm] unit normal (master outward) and surface Jacobian
+  // [nf] where the BR1 interface state of each face node comes from: >= 0 the face node facing it across a
+  // conforming interface (same nodes on both sides); PMG_WLINK_MORTAR a p-nonconforming face (the mortar
+  // pass writes it); <= -2 a boundary face node, -2 - (8 * mortar node + boundary code)
+  const int* __restrict__ wlink;
   const double* __restrict__ T_;      // transfer tables of this family
 };
+#define PMG_WLINK_MORTAR (-1)
 using LevelDev = LevelDevT<double>;
 
 // Dynamic LDS of a templated kernel, viewed in its working type.

@@ -133,16 +133,24 @@ struct Work {
   T *qf = nullptr, *Ws = nullptr, *gW = nullptr, *gf = nullptr, *Phi = nullptr;
 };
 
+// LDS of the gradient kernel in values: W and the metric terms at the tile's nodes, W* at its face nodes.
+static int grad_lds_words(int nodes, int face_nodes) { return 13 * nodes + 4 * face_nodes; }
+static const size_t GRAD_LDS_MAX = 65536;  // bytes
+
 struct Level {
   int K = 0, nn = 0, nf = 0, nm = 0, fam = 0;
   int prec = PREC_F64;  // working precision of the operator and smoother on this level
   std::vector<int> ord, off, fo;
   int ntiles = 0, nftiles = 0, max_tile = 0, tile_target = 256;
+  int grad_words = 0;                      // largest LDS of the gradient kernel over the tiles, in values
+  int nf1tiles = 0;                        // face tiles of p-nonconforming interfaces (face pass 1)
+  int64_t nfl_conf = 0, nfl_bnd = 0, nfl_nc = 0;  // face nodes on conforming / boundary / mortar faces
   int block = PMG_BLOCK;  // threads per element tile: the smallest of 64, 128, 256 that holds the largest tile
   DevArena arena;
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile, *d_ftprob;
   int *d_tprob = nullptr, *d_eoff = nullptr, *d_efo = nullptr;  // per tile / per elist entry
+  int *d_wlink = nullptr, *d_f1list = nullptr;
   int4* d_tiles;
   FaceRec* d_faces;
   double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;  // geometry in FP64 (always kept)
@@ -161,7 +169,7 @@ struct Level {
   }
   size_t wsize() const { return prec == PREC_F32 ? sizeof(float) : sizeof(double); }
   size_t lds_trace() const { return (size_t)5 * max_tile * wsize(); }
-  size_t lds_grad() const { return (size_t)13 * max_tile * wsize(); }
+  size_t lds_grad() const { return (size_t)grad_words * wsize(); }
   // flux rows, plus the updated-state rows of an RK stage when one node per thread (tiles <= block)
   size_t lds_div() const { return (size_t)(max_tile <= block ? 20 : 15) * max_tile * wsize(); }
 };
@@ -319,13 +327,16 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
     buckets[{s->eprob[e], pack3(L.ord[3 * e] + 1, L.ord[3 * e + 1] + 1, L.ord[3 * e + 2] + 1)}].push_back(e);
   std::vector<int> elist;
   std::vector<int4> tiles;
-  int max_tile = 1;
+  int max_tile = 1, grad_words = 1;
   for (auto& kv : buckets) {
     int key = kv.first.second;
     int n1 = key & 255, n2 = (key >> 8) & 255, n3 = key >> 16;
     int npe = n1 * n2 * n3;
+    int fpe = 2 * (n2 * n3 + n1 * n3 + n1 * n2);
     int per = std::max(1, std::min(PMG_MAX_TILE_ELEMS, target / npe));
-    while (per > 1 && per * npe > PMG_TILE_MAX) per--;
+    while (per > 1 && (per * npe > PMG_TILE_MAX || grad_lds_words(per * npe, per * fpe) * L.wsize() > GRAD_LDS_MAX))
+      per--;
+    grad_words = std::max(grad_words, grad_lds_words(per * npe, per * fpe));
     const auto& es = kv.second;
     for (size_t i = 0; i < es.size(); i += per) {
       int cnt = (int)std::min<size_t>(per, es.size() - i);
@@ -335,6 +346,7 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
     }
   }
   REQUIRE(max_tile <= PMG_TILE_MAX, "element tile too large");
+  REQUIRE(grad_words * L.wsize() <= GRAD_LDS_MAX, "element tile too large for LDS");
   std::vector<int> tprob(tiles.size()), eoff(elist.size()), efo(elist.size());
   for (size_t t = 0; t < tiles.size(); t++) tprob[t] = s->eprob[elist[tiles[t].x]];
   for (size_t k = 0; k < elist.size(); k++) {
@@ -350,6 +362,7 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   L.d_efo = L.tile_arena.upload(efo);
   L.ntiles = (int)tiles.size();
   L.max_tile = max_tile;
+  L.grad_words = grad_words;
   L.tile_target = target;
   L.block = max_tile <= 64 ? 64 : (max_tile <= 128 ? 128 : PMG_BLOCK);
   L.dev.tiles = L.dev32.tiles = L.d_tiles;
@@ -419,32 +432,71 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
       }
       faces.push_back(F);
     }
-  // faces ordered by (problem, mortar size) and packed into tiles of <= PMG_FACE_TILE lanes that never
-  // split a face nor mix problems
+  // faces ordered by (problem, p-nonconforming first, mortar size) and packed into tiles of <= PMG_FACE_TILE
+  // lanes that never split a face nor mix problems or conforming with p-nonconforming interfaces
+  auto mortar = [](const FaceRec& F) { return F.eS >= 0 && F.flags != 3; };
   std::stable_sort(faces.begin(), faces.end(), [&](const FaceRec& a, const FaceRec& b) {
     int pa = s->eprob[a.eM], pb = s->eprob[b.eM];
     if (pa != pb) return pa < pb;
+    if (mortar(a) != mortar(b)) return mortar(a);
     return a.ms * a.mt > b.ms * b.mt;
   });
-  std::vector<int> ftile{0}, mface;
+  std::vector<int> ftile{0}, mface, f1list;
   int cur = 0, cur_prob = faces.empty() ? 0 : s->eprob[faces[0].eM];
+  bool cur_mortar = !faces.empty() && mortar(faces[0]);
   for (size_t i = 0; i < faces.size(); i++) {
     int nmf = faces[i].ms * faces[i].mt;
     int p = s->eprob[faces[i].eM];
-    if (cur > 0 && (cur + nmf > PMG_FACE_TILE || p != cur_prob)) {
+    if (cur > 0 && (cur + nmf > PMG_FACE_TILE || p != cur_prob || mortar(faces[i]) != cur_mortar)) {
+      if (cur_mortar) f1list.push_back((int)ftile.size() - 1);
       ftile.push_back((int)mface.size());
       cur = 0;
     }
     cur_prob = p;
+    cur_mortar = mortar(faces[i]);
     faces[i].mbase = (int)mface.size();
     for (int k = 0; k < nmf; k++) mface.push_back((int)i);
     cur += nmf;
   }
-  if (ftile.back() != (int)mface.size()) ftile.push_back((int)mface.size());
+  if (ftile.back() != (int)mface.size()) {
+    if (cur_mortar) f1list.push_back((int)ftile.size() - 1);
+    ftile.push_back((int)mface.size());
+  }
   L->nftiles = (int)ftile.size() - 1;
+  L->nf1tiles = (int)f1list.size();
   std::vector<int> ftprob(std::max(L->nftiles, 1), 0);
   for (int t = 0; t < L->nftiles; t++) ftprob[t] = s->eprob[faces[mface[ftile[t]]].eM];
   L->nm = (int)mface.size();
+  REQUIRE(8ll * L->nm + 16 < (1ll << 31), "mesh too large for 32-bit mortar indexing");
+
+  // source of the BR1 interface state of every face node (the gradient kernel's wlink)
+  std::vector<int> wlink(nf, PMG_WLINK_MORTAR);
+  for (const FaceRec& F : faces) {
+    if (F.eS < 0) {
+      for (int k = 0; k < F.nMs * F.nMt; k++) wlink[F.foM + k] = -2 - (8 * (F.mbase + k) + F.bc);
+      L->nfl_bnd += F.nMs * F.nMt;
+    } else if (!mortar(F)) {
+      // conforming: mortar node (al, be) is master node al + nMs be and slave node i1 + nS1 i2
+      for (int be = 0; be < F.mt; be++)
+        for (int al = 0; al < F.ms; al++) {
+          int i1, i2;
+          if (F.o & 4) {
+            i1 = (F.o & 1) ? F.mt - 1 - be : be;
+            i2 = (F.o & 2) ? F.ms - 1 - al : al;
+          } else {
+            i1 = (F.o & 1) ? F.ms - 1 - al : al;
+            i2 = (F.o & 2) ? F.mt - 1 - be : be;
+          }
+          const int fm = F.foM + al + F.nMs * be, fs = F.foS + i1 + F.nS1 * i2;
+          wlink[fm] = fs;
+          wlink[fs] = fm;
+        }
+      L->nfl_conf += 2 * F.ms * F.mt;
+    } else {
+      L->nfl_nc += F.nMs * F.nMt + F.nS1 * F.nS2;
+    }
+  }
+  REQUIRE(L->nfl_conf + L->nfl_bnd + L->nfl_nc == nf, "face nodes not covered by the interfaces");
 
   std::vector<int> node_elem(nn);
   for (int e = 0; e < K; e++)
@@ -459,6 +511,8 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_mface = A.upload(mface);
   L->d_ftile = A.upload(ftile);
   L->d_ftprob = A.upload(ftprob);
+  L->d_wlink = A.upload(wlink);
+  L->d_f1list = f1list.empty() ? nullptr : A.upload(f1list);
   L->d_Ja = A.alloc<double>(9 * nn);
   L->d_invJ = A.alloc<double>(nn);
   L->d_J = A.alloc<double>(nn);
@@ -494,6 +548,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   D.ord = L->d_ord; D.off = L->d_off; D.fo = L->d_fo;
   D.Ja = L->d_Ja; D.invJ = L->d_invJ; D.J = L->d_J; D.Nout = L->d_Nout;
   D.faces = L->d_faces; D.mface = L->d_mface; D.ftile = L->d_ftile; D.ftprob = L->d_ftprob; D.mgeo = L->d_mgeo;
+  D.wlink = L->d_wlink;
   D.T_ = s->ctx->T[L->fam];
   build_tiles(s, *L, 256);
 
@@ -522,6 +577,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
     F.ptab = D.ptab; F.eprob = D.eprob; F.node_elem = D.node_elem; F.dt = D.dt; F.active = D.active;
     F.ord = D.ord; F.off = D.off; F.fo = D.fo; F.faces = D.faces; F.mface = D.mface; F.ftile = D.ftile;
     F.ftprob = D.ftprob;
+    F.wlink = D.wlink;
     F.T_ = D.T_;
     F.tiles = D.tiles; F.elist = D.elist; F.tprob = D.tprob; F.eoff = D.eoff; F.efo = D.efo;
     auto down = [&](const double* src, size_t n) {
@@ -596,13 +652,14 @@ static void launch_trace(const Level& L, const LevelDevT<T>& D, const T* Q, T* q
 }
 
 template <class T>
-static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const T* Ws, T* gW, T* gf,
-                        hipStream_t st) {
+static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const T* qf, const T* Ws, int isolated,
+                        T* gW, T* gf, hipStream_t st) {
   const size_t lds = L.lds_grad();
-  if (L.block == 64) k_grad<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, Ws, gW, gf);
-  else if (L.block == 128) k_grad<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, Ws, gW, gf);
-  else if (L.max_tile <= PMG_BLOCK) k_grad<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, Ws, gW, gf);
-  else k_grad<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, Ws, gW, gf);
+  if (L.block == 64) k_grad<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf);
+  else if (L.block == 128) k_grad<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf);
+  else if (L.max_tile <= PMG_BLOCK)
+    k_grad<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf);
+  else k_grad<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf);
 }
 
 template <class T>
@@ -613,13 +670,6 @@ static void launch_div(const Level& L, const LevelDevT<T>& D, const T* Q, const 
   else if (L.block == 128) k_div<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, gW, Phi, a);
   else if (L.max_tile <= PMG_BLOCK) k_div<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, gW, Phi, a);
   else k_div<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, gW, Phi, a);
-}
-
-template <class T>
-static void launch_face1_iso(const Level& L, const LevelDevT<T>& D, const T* qf, T* Ws, hipStream_t st) {
-  if (L.block == 64) k_face1_iso<T, 64><<<L.ntiles, 64, 0, st>>>(D, qf, Ws);
-  else if (L.block == 128) k_face1_iso<T, 128><<<L.ntiles, 128, 0, st>>>(D, qf, Ws);
-  else k_face1_iso<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, qf, Ws);
 }
 
 template <class T>
@@ -664,14 +714,17 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
   if (!fresh)
     PROF_LAUNCH(s, PK_TRACE, st, (5 * nn + 5 * nf) * w,
                 launch_trace(L, D, Q, W.qf, st));
-  if (isolated)
-    PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nf) * w,
-                launch_face1_iso(L, D, (const T*)W.qf, W.Ws, st));
-  else
-    PROF_LAUNCH(s, PK_FACE1, st, (5 * nf + 4 * nf) * w,
-                k_face1<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.Ws));
-  PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 7 * nf + 12 * nn + 12 * nf) * w,
-              launch_grad(L, D, Q, (const T*)W.Ws, W.gW, W.gf, st));
+  // BR1 interface state: the mortar pass on p-nonconforming interfaces only; the gradient kernel forms it
+  // on conforming and boundary faces (and everywhere when isolated) from the traces
+  const double ncf = L.nfl_nc, cf = L.nfl_conf, bf = L.nfl_bnd;
+  if (!isolated && L.nf1tiles > 0)
+    PROF_LAUNCH(s, PK_FACE1, st, (5 * ncf + 4 * ncf) * w,
+                k_face1<T><<<L.nf1tiles, PMG_FACE_TILE, 0, st>>>(D, L.d_f1list, W.qf, W.Ws));
+  // gradient: Q, J a, 1/J, N in; grad W and its traces out; W* from the traces (own and facing node, the
+  // link table, the boundary normal) or from the mortar pass
+  const double wsrc = isolated ? 5 * nf : 10 * cf + 8 * bf + 4 * ncf + nf * 4.0 / w;
+  PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 3 * nf + wsrc + 12 * nn + 12 * nf) * w,
+              launch_grad(L, D, Q, (const T*)W.qf, (const T*)W.Ws, isolated ? 1 : 0, W.gW, W.gf, st));
   if (isolated)
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 5 * nf) * w,
                 launch_face2_iso(L, D, (const T*)W.qf, (const T*)W.gf, W.Phi, st));
@@ -1347,9 +1400,10 @@ static LevelCount count_level(const pmg_mesh_s* m, const std::vector<int>& ord, 
     }
   }
   for (auto& kv : buckets) {
-    int key = kv.first.second, npe = (key & 255) * ((key >> 8) & 255) * (key >> 16);
+    int key = kv.first.second, n1 = key & 255, n2 = (key >> 8) & 255, n3 = key >> 16, npe = n1 * n2 * n3;
+    int fpe = 2 * (n2 * n3 + n1 * n3 + n1 * n2);
     int per = std::max(1, std::min(PMG_MAX_TILE_ELEMS, 256 / npe));
-    while (per > 1 && per * npe > PMG_TILE_MAX) per--;
+    while (per > 1 && (per * npe > PMG_TILE_MAX || grad_lds_words(per * npe, per * fpe) * 8.0 > GRAD_LDS_MAX)) per--;
     c.ntiles += (kv.second + per - 1) / per;
   }
   return c;
@@ -1363,6 +1417,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 3 * 4.0 * K + 20.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
+  b += 4.0 * c.nf + 4.0 * (c.nm / 64.0 + 2);  // interface-state links, p-nonconforming face-tile list
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
   b += 4.0 * K + 2 * 16.0 * K;                     // transfer tiles towards this level (upper bound)
   return b;
