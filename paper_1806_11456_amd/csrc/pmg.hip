@@ -151,6 +151,7 @@ struct Level {
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile, *d_ftprob;
   int *d_tprob = nullptr, *d_eoff = nullptr, *d_efo = nullptr;  // per tile / per elist entry
   int *d_wlink = nullptr, *d_f1list = nullptr;
+  int* d_ptile = nullptr;  // [nprob + 1]: the element tiles of each problem (contiguous)
   int4* d_tiles;
   FaceRec* d_faces;
   double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;  // geometry in FP64 (always kept)
@@ -299,6 +300,7 @@ struct pmg_solver_s {
   std::vector<double> history;               // residual checks of the last pmg_solve
   int64_t cycles_total = 0;                  // V-cycles run on the state since creation or restore
   unsigned long long* d_red = nullptr;       // reduction slots [NSLOTS][nprob]
+  unsigned long long* d_part = nullptr;      // [K] per-tile partials of a reduction (at most K tiles)
   double* d_zero = nullptr;                  // [5][nn] zeros (absent source)
   double* d_R = nullptr;                     // [5][nn] top-level scratch residual
   double* d_G = nullptr;                     // [5][nn] top-level RK register
@@ -347,8 +349,13 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   }
   REQUIRE(max_tile <= PMG_TILE_MAX, "element tile too large");
   REQUIRE(grad_words * L.wsize() <= GRAD_LDS_MAX, "element tile too large for LDS");
-  std::vector<int> tprob(tiles.size()), eoff(elist.size()), efo(elist.size());
+  std::vector<int> tprob(tiles.size()), eoff(elist.size()), efo(elist.size()), ptile(s->nprob + 1, 0);
   for (size_t t = 0; t < tiles.size(); t++) tprob[t] = s->eprob[elist[tiles[t].x]];
+  // buckets are ordered by problem first: each problem's tiles are one range
+  for (size_t t = 0; t < tiles.size(); t++) ptile[tprob[t] + 1] = (int)t + 1;
+  for (int p = 0; p < s->nprob; p++) ptile[p + 1] = std::max(ptile[p + 1], ptile[p]);
+  for (size_t t = 1; t < tiles.size(); t++) REQUIRE(tprob[t] >= tprob[t - 1], "element tiles not grouped by problem");
+  REQUIRE((int)tiles.size() <= L.K, "more element tiles than elements");
   for (size_t k = 0; k < elist.size(); k++) {
     eoff[k] = L.off[elist[k]];
     efo[k] = L.fo[6 * elist[k]];
@@ -360,6 +367,7 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   L.d_tprob = L.tile_arena.upload(tprob);
   L.d_eoff = L.tile_arena.upload(eoff);
   L.d_efo = L.tile_arena.upload(efo);
+  L.d_ptile = L.tile_arena.upload(ptile);
   L.ntiles = (int)tiles.size();
   L.max_tile = max_tile;
   L.grad_words = grad_words;
@@ -775,13 +783,22 @@ static double read_slot(const pmg_solver_s* s, int slot, hipStream_t st) {
   return m;
 }
 
+// Per-problem min (dt) or max (norms) of the per-tile partials a kernel of level L left in d_part, into a slot.
+static void reduce_tiles(const pmg_solver_s* s, const Level& L, int slot, bool take_max, const int* act,
+                         hipStream_t st) {
+  const double init = take_max ? 0.0 : INFINITY;
+  unsigned long long bits;
+  memcpy(&bits, &init, sizeof(bits));
+  k_tile_reduce<<<s->nprob, 256, 0, st>>>(s->d_part, L.d_ptile, act, take_max ? 1 : 0, bits, slot_ptr(s, slot));
+}
+
 template <class T>
 static void timestep(const pmg_solver_s* s, Level& L, const T* Q, hipStream_t st, const int* act = nullptr) {
-  reset_slot(s, SLOT_DT, INFINITY, st);
   LevelDevT<T> D = L.devT<T>();
   if (act) D.active = D.skip = act;
   PROF_LAUNCH(s, PK_DT, st, L.nn * (5.0 * sizeof(T) + 16.0),
-              launch_dt(L, D, Q, slot_ptr(s, SLOT_DT), st));
+              launch_dt(L, D, Q, s->d_part, st));
+  reduce_tiles(s, L, SLOT_DT, false, act, st);
 }
 
 template <class T>
@@ -808,11 +825,9 @@ static void residual(const pmg_solver_s* s, Level& L, const T* Q, const T* S, T*
   DivArgs<T> a = div_args<T>(EPI_R);
   a.S = S;
   a.out = out;
-  if (norm_slot >= 0) {
-    reset_slot(s, norm_slot, 0.0, st);
-    a.norm = slot_ptr(s, norm_slot);
-  }
+  if (norm_slot >= 0) a.norm = s->d_part;
   op_eval(s, L, Q, isolated, a, st, act);
+  if (norm_slot >= 0) reduce_tiles(s, L, norm_slot, true, act, st);
 }
 
 // The same on buffers held in the level's own precision.
@@ -1339,6 +1354,7 @@ static pmg_solver_s* create_solver(pmg_ctx ctx, const std::vector<const pmg_mesh
   s->d_act[0] = s->arena.upload(std::vector<int>(n, 1));
   s->d_act[1] = s->arena.upload(std::vector<int>(n, 1));
   s->d_red = s->arena.alloc<unsigned long long>((size_t)NSLOTS * n);
+  s->d_part = s->arena.alloc<unsigned long long>((size_t)K);
   s->top = build_level(s.get(), s->orders);
   std::vector<int> caps;
   if (mg && mg->n_levels > 0 && mg->level_caps) {
@@ -1418,6 +1434,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 3 * 4.0 * K + 20.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
   b += 4.0 * c.nf + 4.0 * (c.nm / 64.0 + 2);  // interface-state links, p-nonconforming face-tile list
+  b += 4.0 * 2;                                // tile range of the problem
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
   b += 4.0 * K + 2 * 16.0 * K;                     // transfer tiles towards this level (upper bound)
   return b;
@@ -1452,7 +1469,7 @@ static double solver_footprint(const pmg_mesh_s* m, const int32_t* orders, const
       if (mixed) extra += level_bytes(c, K, PREC_F64, false);  // the FP64 hierarchy of the precision switch
     }
   }
-  b += sizeof(Phys) + 4.0 * K + 3 * 4.0 + 8.0 * NSLOTS + 3 * 5 * 8.0 * nn_top;  // solver arrays
+  b += sizeof(Phys) + 4.0 * K + 3 * 4.0 + 8.0 * NSLOTS + 8.0 * K + 3 * 5 * 8.0 * nn_top;  // solver arrays
   if (transient) *transient = 12.0 * 8.0 * nn_top;
   if (switch_extra) *switch_extra = extra;
   return b;
