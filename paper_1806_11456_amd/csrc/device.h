@@ -68,9 +68,10 @@ struct LevelDevT {
   const T* __restrict__ invJ;         // [nn]
   const T* __restrict__ J;            // [nn]
   const T* __restrict__ Nout;         // [3][nf] outward normal x surface Jacobian, own side
-  const int4* __restrict__ tiles;     // {first, count, packed n1|n2<<8|n3<<16, nodes}
+  // per element tile, two int4: {first elist entry, elements, packed n1|n2<<8|n3<<16, nodes} and
+  // {problem, first node, first face node, 0} (the bases -1 unless the tile's elements are consecutive)
+  const int4* __restrict__ tiles;
   const int* __restrict__ elist;
-  const int* __restrict__ tprob;      // problem of each tile
   const int* __restrict__ eoff;       // per elist entry: first node of the element (off[elist[k]])
   const int* __restrict__ efo;        // per elist entry: first face node of the element (fo[6 elist[k]])
   const FaceRec* __restrict__ faces;

@@ -149,7 +149,7 @@ struct Level {
   DevArena arena;
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile, *d_ftprob;
-  int *d_tprob = nullptr, *d_eoff = nullptr, *d_efo = nullptr;  // per tile / per elist entry
+  int *d_eoff = nullptr, *d_efo = nullptr;  // per elist entry
   int *d_wlink = nullptr, *d_f1list = nullptr;
   int* d_ptile = nullptr;  // [nprob + 1]: the element tiles of each problem (contiguous)
   int4* d_tiles;
@@ -360,11 +360,23 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
     eoff[k] = L.off[elist[k]];
     efo[k] = L.fo[6 * elist[k]];
   }
+  // tile records: {first elist entry, elements, packed node counts, nodes} and {problem, first node, first
+  // face node, 0}, the bases -1 unless the tile's elements are consecutive in the node and face arrays
+  std::vector<int4> rec(2 * tiles.size());
+  for (size_t t = 0; t < tiles.size(); t++) {
+    const int4 T = tiles[t];
+    const int n1 = T.z & 255, n2 = (T.z >> 8) & 255, n3 = T.z >> 16;
+    const int npe = n1 * n2 * n3, fpe = 2 * (n2 * n3 + n1 * n3 + n1 * n2);
+    bool contiguous = true;
+    for (int c = 0; c < T.y; c++)
+      contiguous = contiguous && eoff[T.x + c] == eoff[T.x] + c * npe && efo[T.x + c] == efo[T.x] + c * fpe;
+    rec[2 * t] = T;
+    rec[2 * t + 1] = make_int4(tprob[t], contiguous ? eoff[T.x] : -1, contiguous ? efo[T.x] : -1, 0);
+  }
   L.tile_arena.~DevArena();
   new (&L.tile_arena) DevArena();
   L.d_elist = L.tile_arena.upload(elist);
-  L.d_tiles = L.tile_arena.upload(tiles);
-  L.d_tprob = L.tile_arena.upload(tprob);
+  L.d_tiles = L.tile_arena.upload(rec);
   L.d_eoff = L.tile_arena.upload(eoff);
   L.d_efo = L.tile_arena.upload(efo);
   L.d_ptile = L.tile_arena.upload(ptile);
@@ -375,7 +387,6 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   L.block = max_tile <= 64 ? 64 : (max_tile <= 128 ? 128 : PMG_BLOCK);
   L.dev.tiles = L.dev32.tiles = L.d_tiles;
   L.dev.elist = L.dev32.elist = L.d_elist;
-  L.dev.tprob = L.dev32.tprob = L.d_tprob;
   L.dev.eoff = L.dev32.eoff = L.d_eoff;
   L.dev.efo = L.dev32.efo = L.d_efo;
 }
@@ -587,7 +598,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
     F.ftprob = D.ftprob;
     F.wlink = D.wlink;
     F.T_ = D.T_;
-    F.tiles = D.tiles; F.elist = D.elist; F.tprob = D.tprob; F.eoff = D.eoff; F.efo = D.efo;
+    F.tiles = D.tiles; F.elist = D.elist; F.eoff = D.eoff; F.efo = D.efo;
     auto down = [&](const double* src, size_t n) {
       float* dst = A.alloc<float>(n);
       k_copy<<<cdiv(n, 256), 256>>>(dst, src, n);
@@ -1432,7 +1443,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0) + 2 * c.nn);  // FP64 geometry
   if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
-  b += 3 * 4.0 * K + 20.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
+  b += 3 * 4.0 * K + 32.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
   b += 4.0 * c.nf + 4.0 * (c.nm / 64.0 + 2);  // interface-state links, p-nonconforming face-tile list
   b += 4.0 * 2;                                // tile range of the problem
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
