@@ -83,6 +83,9 @@ struct LevelDevT {
   // conforming interface (same nodes on both sides); PMG_WLINK_MORTAR a p-nonconforming face (the mortar
   // pass writes it); <= -2 a boundary face node, -2 - (8 * mortar node + boundary code)
   const int* __restrict__ wlink;
+  // [nm] on conforming and boundary faces: {master face node, slave face node or -1 - boundary code} of each
+  // mortar node (the mortar nodes are the face nodes of both sides there)
+  const int2* __restrict__ cmap;
   const double* __restrict__ T_;      // transfer tables of this family
 };
 #define PMG_WLINK_MORTAR (-1)
@@ -215,6 +218,41 @@ __device__ __forceinline__ void ghost_state(const Phys& P, int bc, const T q[5],
   } else {
     freestream(P, g);
   }
+}
+
+// Numerical flux x surface Jacobian at one interface point with master outward unit normal n: the Roe flux
+// minus the BR1 viscous flux {{F^v}} . n.  bc == 0: interior, the slave state qs and gradient gs are given;
+// bc > 0: a boundary, the second state is the ghost state of qm and the viscous flux is the interior one
+// (the adiabatic no-slip wall's without work and heat flux, none on free slip).
+template <class T>
+__device__ __forceinline__ void interface_flux(const Phys& P, int bc, const T qm[5], const T gm[12], const T qs_in[5],
+                                               const T gs[12], const T n[3], T Js, T out[5]) {
+  T qs[5], fv[4], Fm[3][4], Fn[5];
+  if (bc == 0) {
+    T Fs[3][4];
+#pragma unroll
+    for (int v = 0; v < 5; v++) qs[v] = qs_in[v];
+    flux_visc(P, qm, gm, false, Fm);
+    flux_visc(P, qs, gs, false, Fs);
+#pragma unroll
+    for (int v = 0; v < 4; v++)
+      fv[v] = T(0.5) * (Fm[0][v] + Fs[0][v]) * n[0] + T(0.5) * (Fm[1][v] + Fs[1][v]) * n[1] +
+              T(0.5) * (Fm[2][v] + Fs[2][v]) * n[2];
+  } else {
+    ghost_state(P, bc, qm, n, qs);
+    if (bc == 3) {
+#pragma unroll
+      for (int v = 0; v < 4; v++) fv[v] = T(0);
+    } else {
+      flux_visc(P, qm, gm, bc == 1, Fm);
+#pragma unroll
+      for (int v = 0; v < 4; v++) fv[v] = Fm[0][v] * n[0] + Fm[1][v] * n[1] + Fm[2][v] * n[2];
+    }
+  }
+  roe_flux(P, qm, qs, n, Fn);
+  out[0] = Fn[0] * Js;
+#pragma unroll
+  for (int v = 0; v < 4; v++) out[v + 1] = (Fn[v + 1] - fv[v]) * Js;
 }
 
 __device__ __forceinline__ void unpack3(int p, int& n1, int& n2, int& n3) {

@@ -143,14 +143,16 @@ struct Level {
   std::vector<int> ord, off, fo;
   int ntiles = 0, nftiles = 0, max_tile = 0, tile_target = 256;
   int grad_words = 0;                      // largest LDS of the gradient kernel over the tiles, in values
-  int nf1tiles = 0;                        // face tiles of p-nonconforming interfaces (face pass 1)
+  int nf1tiles = 0;                        // face tiles of p-nonconforming interfaces (mortar passes)
+  int nfctiles = 0;                        // face tiles of conforming interfaces and boundaries
   int64_t nfl_conf = 0, nfl_bnd = 0, nfl_nc = 0;  // face nodes on conforming / boundary / mortar faces
   int block = PMG_BLOCK;  // threads per element tile: the smallest of 64, 128, 256 that holds the largest tile
   DevArena arena;
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile, *d_ftprob;
   int *d_eoff = nullptr, *d_efo = nullptr;  // per elist entry
-  int *d_wlink = nullptr, *d_f1list = nullptr;
+  int *d_wlink = nullptr, *d_f1list = nullptr, *d_fclist = nullptr;
+  int2* d_cmap = nullptr;
   int* d_ptile = nullptr;  // [nprob + 1]: the element tiles of each problem (contiguous)
   int4* d_tiles;
   FaceRec* d_faces;
@@ -483,16 +485,27 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   }
   L->nftiles = (int)ftile.size() - 1;
   L->nf1tiles = (int)f1list.size();
+  std::vector<int> fclist;
+  for (int t = 0, k = 0; t < L->nftiles; t++) {
+    if (k < L->nf1tiles && f1list[k] == t) k++;
+    else fclist.push_back(t);
+  }
+  L->nfctiles = (int)fclist.size();
   std::vector<int> ftprob(std::max(L->nftiles, 1), 0);
   for (int t = 0; t < L->nftiles; t++) ftprob[t] = s->eprob[faces[mface[ftile[t]]].eM];
   L->nm = (int)mface.size();
   REQUIRE(8ll * L->nm + 16 < (1ll << 31), "mesh too large for 32-bit mortar indexing");
 
   // source of the BR1 interface state of every face node (the gradient kernel's wlink)
+  // and the face nodes of each mortar node of conforming and boundary faces (the flat flux pass's cmap)
   std::vector<int> wlink(nf, PMG_WLINK_MORTAR);
+  std::vector<int2> cmap(std::max(L->nm, 1), make_int2(-1, -1));
   for (const FaceRec& F : faces) {
     if (F.eS < 0) {
-      for (int k = 0; k < F.nMs * F.nMt; k++) wlink[F.foM + k] = -2 - (8 * (F.mbase + k) + F.bc);
+      for (int k = 0; k < F.nMs * F.nMt; k++) {
+        wlink[F.foM + k] = -2 - (8 * (F.mbase + k) + F.bc);
+        cmap[F.mbase + k] = make_int2(F.foM + k, -1 - F.bc);
+      }
       L->nfl_bnd += F.nMs * F.nMt;
     } else if (!mortar(F)) {
       // conforming: mortar node (al, be) is master node al + nMs be and slave node i1 + nS1 i2
@@ -509,6 +522,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
           const int fm = F.foM + al + F.nMs * be, fs = F.foS + i1 + F.nS1 * i2;
           wlink[fm] = fs;
           wlink[fs] = fm;
+          cmap[F.mbase + al + F.ms * be] = make_int2(fm, fs);
         }
       L->nfl_conf += 2 * F.ms * F.mt;
     } else {
@@ -532,6 +546,8 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_ftprob = A.upload(ftprob);
   L->d_wlink = A.upload(wlink);
   L->d_f1list = f1list.empty() ? nullptr : A.upload(f1list);
+  L->d_fclist = fclist.empty() ? nullptr : A.upload(fclist);
+  L->d_cmap = A.upload(cmap);
   L->d_Ja = A.alloc<double>(9 * nn);
   L->d_invJ = A.alloc<double>(nn);
   L->d_J = A.alloc<double>(nn);
@@ -568,6 +584,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   D.Ja = L->d_Ja; D.invJ = L->d_invJ; D.J = L->d_J; D.Nout = L->d_Nout;
   D.faces = L->d_faces; D.mface = L->d_mface; D.ftile = L->d_ftile; D.ftprob = L->d_ftprob; D.mgeo = L->d_mgeo;
   D.wlink = L->d_wlink;
+  D.cmap = L->d_cmap;
   D.T_ = s->ctx->T[L->fam];
   build_tiles(s, *L, 256);
 
@@ -597,6 +614,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
     F.ord = D.ord; F.off = D.off; F.fo = D.fo; F.faces = D.faces; F.mface = D.mface; F.ftile = D.ftile;
     F.ftprob = D.ftprob;
     F.wlink = D.wlink;
+    F.cmap = D.cmap;
     F.T_ = D.T_;
     F.tiles = D.tiles; F.elist = D.elist; F.eoff = D.eoff; F.efo = D.efo;
     auto down = [&](const double* src, size_t n) {
@@ -744,12 +762,19 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
   const double wsrc = isolated ? 5 * nf : 10 * cf + 8 * bf + 4 * ncf + nf * 4.0 / w;
   PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 3 * nf + wsrc + 12 * nn + 12 * nf) * w,
               launch_grad(L, D, Q, (const T*)W.qf, (const T*)W.Ws, isolated ? 1 : 0, W.gW, W.gf, st));
-  if (isolated)
+  if (isolated) {
     PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 5 * nf) * w,
                 launch_face2_iso(L, D, (const T*)W.qf, (const T*)W.gf, W.Phi, st));
-  else
-    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 4 * nm + 5 * nf) * w,
-                k_face2<T><<<L.nftiles, PMG_FACE_TILE, 0, st>>>(D, W.qf, W.gf, W.Phi));
+  } else {
+    // numerical flux: the flat pass on conforming and boundary faces, the mortar pass on the others
+    const double cbf = cf + bf, cm = cf / 2 + bf;  // face nodes and mortar nodes there
+    if (L.nfctiles > 0)
+      PROF_LAUNCH(s, PK_FACE2, st, (17 * cbf + 4 * cm + 5 * cbf) * w + 8 * cm,
+                  k_face2c<T><<<L.nfctiles, PMG_FACE_TILE, 0, st>>>(D, L.d_fclist, W.qf, W.gf, W.Phi));
+    if (L.nf1tiles > 0)
+      PROF_LAUNCH(s, PK_FACE2, st, (17 * ncf + 4 * (nm - cm) + 5 * ncf) * w,
+                  k_face2<T><<<L.nf1tiles, PMG_FACE_TILE, 0, st>>>(D, L.d_f1list, W.qf, W.gf, W.Phi));
+  }
   // divergence: Q, grad W, J a, 1/J, Phi in; the epilogue's own arrays
   double epi = 0.0;
   switch (a.mode) {
@@ -1444,7 +1469,8 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 3 * 4.0 * K + 32.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
-  b += 4.0 * c.nf + 4.0 * (c.nm / 64.0 + 2);  // interface-state links, p-nonconforming face-tile list
+  b += 4.0 * c.nf + 4.0 * (c.nm / 64.0 + 2);  // interface-state links, face-tile lists
+  b += 8.0 * std::max(c.nm, 1.0);              // face nodes of the conforming mortar nodes
   b += 4.0 * 2;                                // tile range of the problem
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
   b += 4.0 * K + 2 * 16.0 * K;                     // transfer tiles towards this level (upper bound)
