@@ -109,6 +109,7 @@ inline int pack3(int a, int b, int c) { return a | (b << 8) | (c << 16); }
 // ------------------------------------------------------------------------------------------------
 struct pmg_ctx_s {
   int device = 0;
+  int lds_max = 65536;  // LDS bytes one workgroup may allocate on the device
   DevArena arena;
   double* T[2] = {nullptr, nullptr};  // transfer tables per family
   std::map<std::string, int> tile_cache;  // autotuned tile targets keyed by level structure
@@ -133,9 +134,11 @@ struct Work {
   T *qf = nullptr, *Ws = nullptr, *gW = nullptr, *gf = nullptr, *Phi = nullptr;
 };
 
-// LDS of the gradient kernel in values: W and the metric terms at the tile's nodes, W* at its face nodes.
-static int grad_lds_words(int nodes, int face_nodes) { return 13 * nodes + 4 * face_nodes; }
-static const size_t GRAD_LDS_MAX = 65536;  // bytes
+// LDS of the gradient kernel in values: W and the metric terms at the tile's nodes, W* and the normals at
+// its face nodes.
+static int grad_lds_words(int nodes, int face_nodes) { return 13 * nodes + 7 * face_nodes; }
+// LDS of the divergence kernel: the nodal fluxes, and Phi at the face nodes (or the updated state at the nodes).
+static int div_lds_words(int nodes, int face_nodes) { return 15 * nodes + 5 * std::max(nodes, face_nodes); }
 
 struct Level {
   int K = 0, nn = 0, nf = 0, nm = 0, fam = 0;
@@ -143,6 +146,7 @@ struct Level {
   std::vector<int> ord, off, fo;
   int ntiles = 0, nftiles = 0, max_tile = 0, tile_target = 256;
   int grad_words = 0;                      // largest LDS of the gradient kernel over the tiles, in values
+  int div_words = 0;                       // the same for the divergence kernel
   int nf1tiles = 0;                        // face tiles of p-nonconforming interfaces (mortar passes)
   int nfctiles = 0;                        // face tiles of conforming interfaces and boundaries
   int64_t nfl_conf = 0, nfl_bnd = 0, nfl_nc = 0;  // face nodes on conforming / boundary / mortar faces
@@ -173,8 +177,7 @@ struct Level {
   size_t wsize() const { return prec == PREC_F32 ? sizeof(float) : sizeof(double); }
   size_t lds_trace() const { return (size_t)5 * max_tile * wsize(); }
   size_t lds_grad() const { return (size_t)grad_words * wsize(); }
-  // flux rows, plus the updated-state rows of an RK stage when one node per thread (tiles <= block)
-  size_t lds_div() const { return (size_t)(max_tile <= block ? 20 : 15) * max_tile * wsize(); }
+  size_t lds_div() const { return (size_t)div_words * wsize(); }
 };
 
 struct XferTiles {
@@ -331,16 +334,20 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
     buckets[{s->eprob[e], pack3(L.ord[3 * e] + 1, L.ord[3 * e + 1] + 1, L.ord[3 * e + 2] + 1)}].push_back(e);
   std::vector<int> elist;
   std::vector<int4> tiles;
-  int max_tile = 1, grad_words = 1;
+  int max_tile = 1, grad_words = 1, div_words = 1;
   for (auto& kv : buckets) {
     int key = kv.first.second;
     int n1 = key & 255, n2 = (key >> 8) & 255, n3 = key >> 16;
     int npe = n1 * n2 * n3;
     int fpe = 2 * (n2 * n3 + n1 * n3 + n1 * n2);
     int per = std::max(1, std::min(PMG_MAX_TILE_ELEMS, target / npe));
-    while (per > 1 && (per * npe > PMG_TILE_MAX || grad_lds_words(per * npe, per * fpe) * L.wsize() > GRAD_LDS_MAX))
-      per--;
+    auto lds_fits = [&](int c) {
+      return (size_t)std::max(grad_lds_words(c * npe, c * fpe), div_lds_words(c * npe, c * fpe)) * L.wsize() <=
+             (size_t)s->ctx->lds_max;
+    };
+    while (per > 1 && (per * npe > PMG_TILE_MAX || !lds_fits(per))) per--;
     grad_words = std::max(grad_words, grad_lds_words(per * npe, per * fpe));
+    div_words = std::max(div_words, div_lds_words(per * npe, per * fpe));
     const auto& es = kv.second;
     for (size_t i = 0; i < es.size(); i += per) {
       int cnt = (int)std::min<size_t>(per, es.size() - i);
@@ -350,7 +357,8 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
     }
   }
   REQUIRE(max_tile <= PMG_TILE_MAX, "element tile too large");
-  REQUIRE(grad_words * L.wsize() <= GRAD_LDS_MAX, "element tile too large for LDS");
+  REQUIRE((size_t)std::max(grad_words, div_words) * L.wsize() <= (size_t)s->ctx->lds_max,
+          "element tile too large for the device's LDS");
   std::vector<int> tprob(tiles.size()), eoff(elist.size()), efo(elist.size()), ptile(s->nprob + 1, 0);
   for (size_t t = 0; t < tiles.size(); t++) tprob[t] = s->eprob[elist[tiles[t].x]];
   // buckets are ordered by problem first: each problem's tiles are one range
@@ -385,6 +393,7 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   L.ntiles = (int)tiles.size();
   L.max_tile = max_tile;
   L.grad_words = grad_words;
+  L.div_words = div_words;
   L.tile_target = target;
   L.block = max_tile <= 64 ? 64 : (max_tile <= 128 ? 128 : PMG_BLOCK);
   L.dev.tiles = L.dev32.tiles = L.d_tiles;
@@ -1455,7 +1464,10 @@ static LevelCount count_level(const pmg_mesh_s* m, const std::vector<int>& ord, 
     int key = kv.first.second, n1 = key & 255, n2 = (key >> 8) & 255, n3 = key >> 16, npe = n1 * n2 * n3;
     int fpe = 2 * (n2 * n3 + n1 * n3 + n1 * n2);
     int per = std::max(1, std::min(PMG_MAX_TILE_ELEMS, 256 / npe));
-    while (per > 1 && (per * npe > PMG_TILE_MAX || grad_lds_words(per * npe, per * fpe) * 8.0 > GRAD_LDS_MAX)) per--;
+    while (per > 1 && (per * npe > PMG_TILE_MAX ||
+                       std::max(grad_lds_words(per * npe, per * fpe), div_lds_words(per * npe, per * fpe)) * 8.0 >
+                           m->ctx->lds_max))
+      per--;
     c.ntiles += (kv.second + per - 1) / per;
   }
   return c;
@@ -1528,6 +1540,7 @@ pmg_status pmg_ctx_create(int hip_device, pmg_ctx* out) {
     HIPCHECK(hipSetDevice(hip_device));
     auto c = std::make_unique<pmg_ctx_s>();
     c->device = hip_device;
+    HIPCHECK(hipDeviceGetAttribute(&c->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device));
     BasisTables B[2];
     std::vector<double> T(TMAT_STRIDE);
     for (int fam = 0; fam < 2; fam++) {
