@@ -155,7 +155,8 @@ struct Level {
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile, *d_ftprob;
   int *d_eoff = nullptr, *d_efo = nullptr;  // per elist entry
-  int *d_wlink = nullptr, *d_f1list = nullptr, *d_fclist = nullptr;
+  int *d_wlink = nullptr, *d_f1list = nullptr;
+  int4* d_fcrec = nullptr;  // conforming / boundary face tiles: {first mortar node, end, problem, 0}
   int2* d_cmap = nullptr;
   int* d_ptile = nullptr;  // [nprob + 1]: the element tiles of each problem (contiguous)
   int4* d_tiles;
@@ -555,7 +556,9 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_ftprob = A.upload(ftprob);
   L->d_wlink = A.upload(wlink);
   L->d_f1list = f1list.empty() ? nullptr : A.upload(f1list);
-  L->d_fclist = fclist.empty() ? nullptr : A.upload(fclist);
+  std::vector<int4> fcrec;
+  for (int t : fclist) fcrec.push_back(make_int4(ftile[t], ftile[t + 1], ftprob[t], 0));
+  L->d_fcrec = fcrec.empty() ? nullptr : A.upload(fcrec);
   L->d_cmap = A.upload(cmap);
   L->d_Ja = A.alloc<double>(9 * nn);
   L->d_invJ = A.alloc<double>(nn);
@@ -779,7 +782,7 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
     const double cbf = cf + bf, cm = cf / 2 + bf;  // face nodes and mortar nodes there
     if (L.nfctiles > 0)
       PROF_LAUNCH(s, PK_FACE2, st, (17 * cbf + 4 * cm + 5 * cbf) * w + 8 * cm,
-                  k_face2c<T><<<L.nfctiles, PMG_FACE_TILE, 0, st>>>(D, L.d_fclist, W.qf, W.gf, W.Phi));
+                  k_face2c<T><<<L.nfctiles, PMG_FACE_TILE, 0, st>>>(D, L.d_fcrec, W.qf, W.gf, W.Phi));
     if (L.nf1tiles > 0)
       PROF_LAUNCH(s, PK_FACE2, st, (17 * ncf + 4 * (nm - cm) + 5 * ncf) * w,
                   k_face2<T><<<L.nf1tiles, PMG_FACE_TILE, 0, st>>>(D, L.d_f1list, W.qf, W.gf, W.Phi));
@@ -1481,7 +1484,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 3 * 4.0 * K + 32.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
-  b += 4.0 * c.nf + 4.0 * (c.nm / 64.0 + 2);  // interface-state links, face-tile lists
+  b += 4.0 * c.nf + 16.0 * (c.nm / 64.0 + 2);  // interface-state links, face-tile list and records
   b += 8.0 * std::max(c.nm, 1.0);              // face nodes of the conforming mortar nodes
   b += 4.0 * 2;                                // tile range of the problem
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
