@@ -665,13 +665,22 @@ static std::unique_ptr<XferTiles> build_xfer(const pmg_solver_s* s, const Level&
     const auto& es = kv.second;
     for (size_t i = 0; i < es.size(); i += per) {
       int cnt = (int)std::min<size_t>(per, es.size() - i);
+      // direct node bases when the tile's elements are consecutive on a level
+      bool cf = true, cc = true;
+      for (int c = 0; c < cnt; c++) {
+        cf = cf && fine.off[es[i + c]] == fine.off[es[i]] + c * na;
+        cc = cc && coarse.off[es[i + c]] == coarse.off[es[i]] + c * nb;
+      }
+      const int bf = cf ? fine.off[es[i]] : -1, bc = cc ? coarse.off[es[i]] : -1;
       tr.push_back(make_int4((int)elist.size(), cnt, a, b));
+      tr.push_back(make_int4(bf, bc, 0, 0));
       tp.push_back(make_int4((int)elist.size(), cnt, b, a));
+      tp.push_back(make_int4(bc, bf, 0, 0));
       stride = std::max(stride, cnt * big);
       for (int c = 0; c < cnt; c++) elist.push_back(es[i + c]);
     }
   }
-  X->ntiles = (int)tr.size();
+  X->ntiles = (int)tr.size() / 2;
   X->lds_stride = stride;
   X->d_restrict = X->arena.upload(tr);
   X->d_prolong = X->arena.upload(tp);
@@ -895,7 +904,8 @@ static void residual_any(const pmg_solver_s* s, Level& L, const void* Q, const v
 
 template <class TU, class TV>
 static void xfer_t(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
-                   const TU* U, const TU* U0, TV* V, bool accumulate, hipStream_t st) {
+                   const TU* U, const TU* U0, TV* V, bool accumulate, hipStream_t st, TV* V0 = nullptr,
+                   const TU* U2 = nullptr, TV* V2 = nullptr) {
   traces_stale(s);  // V may be a state whose traces are held
   XferArgs<TU, TV> a;
   a.tiles = prolong ? X.d_prolong : X.d_restrict;
@@ -908,25 +918,38 @@ static void xfer_t(const pmg_solver_s* s, const Level& from, const Level& to, co
   a.U = U;
   a.U0 = U0;
   a.V = V;
+  a.V0 = V0;
+  a.U2 = U2;
+  a.V2 = V2;
   a.accumulate = accumulate ? 1 : 0;
   a.lds_stride = X.lds_stride;
-  PROF_LAUNCH(s, PK_XFER, st,
-              5.0 * from.nn * (U0 ? 2 : 1) * sizeof(TU) + 5.0 * to.nn * (accumulate ? 2 : 1) * sizeof(TV),
-              k_transfer<TU, TV><<<X.ntiles, PMG_BLOCK, (size_t)10 * X.lds_stride * sizeof(double), st>>>(a));
+  const double bytes = 5.0 * from.nn * ((U0 ? 2 : 1) + (U2 ? 1 : 0)) * sizeof(TU) +
+                       5.0 * to.nn * ((accumulate ? 2 : 1) + (V0 ? 1 : 0) + (V2 ? 1 : 0)) * sizeof(TV);
+  if (U2)
+    PROF_LAUNCH(s, PK_XFER, st, bytes,
+                k_transfer<TU, TV, 10><<<X.ntiles, PMG_BLOCK, (size_t)20 * X.lds_stride * sizeof(double), st>>>(a));
+  else
+    PROF_LAUNCH(s, PK_XFER, st, bytes,
+                k_transfer<TU, TV, 5><<<X.ntiles, PMG_BLOCK, (size_t)10 * X.lds_stride * sizeof(double), st>>>(a));
 }
 
-// Transfer between two levels; 'U', 'U0' in the precision of 'from', 'V' in that of 'to'.
+// Transfer between two levels; 'U', 'U0' (and 'U2') in the precision of 'from', 'V' ('V0', 'V2') in that of 'to'.
 static void xfer(const pmg_solver_s* s, const Level& from, const Level& to, const XferTiles& X, bool prolong,
-                 const void* U, const void* U0, void* V, bool accumulate, hipStream_t st) {
+                 const void* U, const void* U0, void* V, bool accumulate, hipStream_t st, void* V0 = nullptr,
+                 const void* U2 = nullptr, void* V2 = nullptr) {
   const bool f32 = from.prec == PREC_F32, t32 = to.prec == PREC_F32;
   if (f32 && t32)
-    xfer_t(s, from, to, X, prolong, (const float*)U, (const float*)U0, (float*)V, accumulate, st);
+    xfer_t(s, from, to, X, prolong, (const float*)U, (const float*)U0, (float*)V, accumulate, st, (float*)V0,
+           (const float*)U2, (float*)V2);
   else if (f32)
-    xfer_t(s, from, to, X, prolong, (const float*)U, (const float*)U0, (double*)V, accumulate, st);
+    xfer_t(s, from, to, X, prolong, (const float*)U, (const float*)U0, (double*)V, accumulate, st, (double*)V0,
+           (const float*)U2, (double*)V2);
   else if (t32)
-    xfer_t(s, from, to, X, prolong, (const double*)U, (const double*)U0, (float*)V, accumulate, st);
+    xfer_t(s, from, to, X, prolong, (const double*)U, (const double*)U0, (float*)V, accumulate, st, (float*)V0,
+           (const double*)U2, (float*)V2);
   else
-    xfer_t(s, from, to, X, prolong, (const double*)U, (const double*)U0, (double*)V, accumulate, st);
+    xfer_t(s, from, to, X, prolong, (const double*)U, (const double*)U0, (double*)V, accumulate, st, (double*)V0,
+           (const double*)U2, (double*)V2);
 }
 
 // Transfer of caller-owned FP64 fields, whatever the levels' working precision.
@@ -1170,14 +1193,15 @@ static void vcycle_rec(CycleCtx& c, int l, int top) {
       coarse_source<double>(c, l);
     }
   }
-  // Q~0: the restricted state (on an FP32 level, the FP64 restriction rounded once); the correction
-  // Q~ - Q~0 is formed in the level's precision and added to the finer level in its precision
-  copy_level(L, H.Q0[l], H.Q[l], c.st);
+  // Q~0: the restricted state (on an FP32 level, the FP64 restriction rounded once), written by the
+  // restriction with Q~; the correction Q~ - Q~0 is formed in the level's precision and added to the finer
+  // level in its precision
   double rpre = pre_smooth(c, l, top);
   if (l > 0) {
     Level& Lc = *H.lv[l - 1];
-    xfer(s, L, Lc, *H.xf[l - 1], false, H.Q[l], nullptr, H.Q[l - 1], false, c.st);
-    if (!s->mg.tuning) xfer(s, L, Lc, *H.xf[l - 1], false, H.R[l], nullptr, H.r[l - 1], false, c.st);
+    // the state and the residual restricted in one launch
+    xfer(s, L, Lc, *H.xf[l - 1], false, H.Q[l], nullptr, H.Q[l - 1], false, c.st, H.Q0[l - 1],
+         s->mg.tuning ? nullptr : H.R[l], s->mg.tuning ? nullptr : H.r[l - 1]);
     vcycle_rec(c, l - 1, top);
     // Q <- Q + I (Q~c - Q~c_0)   (eqs. FASIterError, FASCorrectSol)
     xfer(s, Lc, L, *H.xf[l - 1], true, H.Q[l - 1], H.Q0[l - 1], H.Q[l], true, c.st);
@@ -1488,7 +1512,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   b += 8.0 * std::max(c.nm, 1.0);              // face nodes of the conforming mortar nodes
   b += 4.0 * 2;                                // tile range of the problem
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
-  b += 4.0 * K + 2 * 16.0 * K;                     // transfer tiles towards this level (upper bound)
+  b += 4.0 * K + 2 * 32.0 * K;                     // transfer tiles towards this level (upper bound)
   return b;
 }
 
