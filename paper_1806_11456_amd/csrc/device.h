@@ -83,6 +83,8 @@ struct LevelDevT {
   // conforming interface (same nodes on both sides); PMG_WLINK_MORTAR a p-nonconforming face (the mortar
   // pass writes it); <= -2 a boundary face node, -2 - (8 * mortar node + boundary code)
   const int* __restrict__ wlink;
+  // [nf] on conforming interior faces: the mortar node (interface point) of each face node, -1 elsewhere
+  const int* __restrict__ mlink;
   // [nm] on conforming and boundary faces: {master face node, slave face node or -1 - boundary code} of each
   // mortar node (the mortar nodes are the face nodes of both sides there)
   const int2* __restrict__ cmap;
@@ -248,6 +250,24 @@ __device__ __forceinline__ void interface_flux(const Phys& P, int bc, const T qm
 #pragma unroll
       for (int v = 0; v < 4; v++) fv[v] = Fm[0][v] * n[0] + Fm[1][v] * n[1] + Fm[2][v] * n[2];
     }
+  }
+  roe_flux(P, qm, qs, n, Fn);
+  out[0] = Fn[0] * Js;
+#pragma unroll
+  for (int v = 0; v < 4; v++) out[v + 1] = (Fn[v + 1] - fv[v]) * Js;
+}
+
+// The same with the viscous part given: fv = {{F^v}} . n (interior) or the boundary's F^v . n, already formed
+// from each side's viscous flux dotted with the master unit normal; bc > 0: the second state is the ghost.
+template <class T>
+__device__ __forceinline__ void interface_flux_fv(const Phys& P, int bc, const T qm[5], const T qs_in[5],
+                                                  const T n[3], T Js, const T fv[4], T out[5]) {
+  T qs[5], Fn[5];
+  if (bc == 0) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) qs[v] = qs_in[v];
+  } else {
+    ghost_state(P, bc, qm, n, qs);
   }
   roe_flux(P, qm, qs, n, Fn);
   out[0] = Fn[0] * Js;

@@ -132,6 +132,7 @@ enum { PREC_F64 = 0, PREC_F32 = 1 };
 template <class T>
 struct Work {
   T *qf = nullptr, *Ws = nullptr, *gW = nullptr, *gf = nullptr, *Phi = nullptr;
+  T* fvn = nullptr;  // [4][nf] each side's F^v . n on conforming and boundary faces
 };
 
 // LDS of the gradient kernel in values: W and the metric terms at the tile's nodes, W* and the normals at
@@ -155,7 +156,7 @@ struct Level {
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile, *d_ftprob;
   int *d_eoff = nullptr, *d_efo = nullptr;  // per elist entry
-  int *d_wlink = nullptr, *d_f1list = nullptr;
+  int *d_wlink = nullptr, *d_mlink = nullptr, *d_f1list = nullptr;
   int4* d_fcrec = nullptr;  // conforming / boundary face tiles: {first mortar node, end, problem, 0}
   int2* d_cmap = nullptr;
   int* d_ptile = nullptr;  // [nprob + 1]: the element tiles of each problem (contiguous)
@@ -508,7 +509,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
 
   // source of the BR1 interface state of every face node (the gradient kernel's wlink)
   // and the face nodes of each mortar node of conforming and boundary faces (the flat flux pass's cmap)
-  std::vector<int> wlink(nf, PMG_WLINK_MORTAR);
+  std::vector<int> wlink(nf, PMG_WLINK_MORTAR), mlink(nf, -1);
   std::vector<int2> cmap(std::max(L->nm, 1), make_int2(-1, -1));
   for (const FaceRec& F : faces) {
     if (F.eS < 0) {
@@ -532,6 +533,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
           const int fm = F.foM + al + F.nMs * be, fs = F.foS + i1 + F.nS1 * i2;
           wlink[fm] = fs;
           wlink[fs] = fm;
+          mlink[fm] = mlink[fs] = F.mbase + al + F.ms * be;
           cmap[F.mbase + al + F.ms * be] = make_int2(fm, fs);
         }
       L->nfl_conf += 2 * F.ms * F.mt;
@@ -555,6 +557,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   L->d_ftile = A.upload(ftile);
   L->d_ftprob = A.upload(ftprob);
   L->d_wlink = A.upload(wlink);
+  L->d_mlink = A.upload(mlink);
   L->d_f1list = f1list.empty() ? nullptr : A.upload(f1list);
   std::vector<int4> fcrec;
   for (int t : fclist) fcrec.push_back(make_int4(ftile[t], ftile[t + 1], ftprob[t], 0));
@@ -576,12 +579,13 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
     W.Ws = A.alloc<double>(4 * nf);
     W.gW = A.alloc<double>(12 * nn);
     W.gf = A.alloc<double>(12 * nf);
+    W.fvn = A.alloc<double>(4 * nf);
     W.Phi = A.alloc<double>(5 * nf);
   } else {
     const Work<double>& T = s->top->w64;
     REQUIRE(nn <= s->top->nn && nf <= s->top->nf, "coarse level larger than the finest");
     if (prec == PREC_F32)
-      L->w32 = Work<float>{(float*)T.qf, (float*)T.Ws, (float*)T.gW, (float*)T.gf, (float*)T.Phi};
+      L->w32 = Work<float>{(float*)T.qf, (float*)T.Ws, (float*)T.gW, (float*)T.gf, (float*)T.Phi, (float*)T.fvn};
     else
       L->w64 = T;
   }
@@ -596,6 +600,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
   D.Ja = L->d_Ja; D.invJ = L->d_invJ; D.J = L->d_J; D.Nout = L->d_Nout;
   D.faces = L->d_faces; D.mface = L->d_mface; D.ftile = L->d_ftile; D.ftprob = L->d_ftprob; D.mgeo = L->d_mgeo;
   D.wlink = L->d_wlink;
+  D.mlink = L->d_mlink;
   D.cmap = L->d_cmap;
   D.T_ = s->ctx->T[L->fam];
   build_tiles(s, *L, 256);
@@ -626,6 +631,7 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
     F.ord = D.ord; F.off = D.off; F.fo = D.fo; F.faces = D.faces; F.mface = D.mface; F.ftile = D.ftile;
     F.ftprob = D.ftprob;
     F.wlink = D.wlink;
+    F.mlink = D.mlink;
     F.cmap = D.cmap;
     F.T_ = D.T_;
     F.tiles = D.tiles; F.elist = D.elist; F.eoff = D.eoff; F.efo = D.efo;
@@ -711,13 +717,13 @@ static void launch_trace(const Level& L, const LevelDevT<T>& D, const T* Q, T* q
 
 template <class T>
 static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const T* qf, const T* Ws, int isolated,
-                        T* gW, T* gf, hipStream_t st) {
+                        T* gW, T* gf, T* fvn, hipStream_t st) {
   const size_t lds = L.lds_grad();
-  if (L.block == 64) k_grad<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf);
-  else if (L.block == 128) k_grad<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf);
+  if (L.block == 64) k_grad<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn);
+  else if (L.block == 128) k_grad<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn);
   else if (L.max_tile <= PMG_BLOCK)
-    k_grad<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf);
-  else k_grad<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf);
+    k_grad<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn);
+  else k_grad<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn);
 }
 
 template <class T>
@@ -731,11 +737,11 @@ static void launch_div(const Level& L, const LevelDevT<T>& D, const T* Q, const 
 }
 
 template <class T>
-static void launch_face2_iso(const Level& L, const LevelDevT<T>& D, const T* qf, const T* gf, T* Phi,
+static void launch_face2_iso(const Level& L, const LevelDevT<T>& D, const T* qf, const T* fvn, T* Phi,
                              hipStream_t st) {
-  if (L.block == 64) k_face2_iso<T, 64><<<L.ntiles, 64, 0, st>>>(D, qf, gf, Phi);
-  else if (L.block == 128) k_face2_iso<T, 128><<<L.ntiles, 128, 0, st>>>(D, qf, gf, Phi);
-  else k_face2_iso<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, qf, gf, Phi);
+  if (L.block == 64) k_face2_iso<T, 64><<<L.ntiles, 64, 0, st>>>(D, qf, fvn, Phi);
+  else if (L.block == 128) k_face2_iso<T, 128><<<L.ntiles, 128, 0, st>>>(D, qf, fvn, Phi);
+  else k_face2_iso<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, qf, fvn, Phi);
 }
 
 template <class T>
@@ -780,18 +786,21 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
                 k_face1<T><<<L.nf1tiles, PMG_FACE_TILE, 0, st>>>(D, L.d_f1list, W.qf, W.Ws));
   // gradient: Q, J a, 1/J, N in; grad W and its traces out; W* from the traces (own and facing node, the
   // link table, the boundary normal) or from the mortar pass
+  // face values of the gradient: the trace on mortar faces, F^v . n (own trace again, interface normal and
+  // link) elsewhere
   const double wsrc = isolated ? 5 * nf : 10 * cf + 8 * bf + 4 * ncf + nf * 4.0 / w;
-  PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 3 * nf + wsrc + 12 * nn + 12 * nf) * w,
-              launch_grad(L, D, Q, (const T*)W.qf, (const T*)W.Ws, isolated ? 1 : 0, W.gW, W.gf, st));
+  const double gout = isolated ? 5 * nf + 4 * nf : 12 * ncf + (cf + bf) * (5 + 3 + 4) + cf * 4.0 / w;
+  PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 3 * nf + wsrc + 12 * nn + gout) * w,
+              launch_grad(L, D, Q, (const T*)W.qf, (const T*)W.Ws, isolated ? 1 : 0, W.gW, W.gf, W.fvn, st));
   if (isolated) {
-    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 12 * nf + 3 * nf + 5 * nf) * w,
-                launch_face2_iso(L, D, (const T*)W.qf, (const T*)W.gf, W.Phi, st));
+    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 4 * nf + 3 * nf + 5 * nf) * w,
+                launch_face2_iso(L, D, (const T*)W.qf, (const T*)W.fvn, W.Phi, st));
   } else {
     // numerical flux: the flat pass on conforming and boundary faces, the mortar pass on the others
     const double cbf = cf + bf, cm = cf / 2 + bf;  // face nodes and mortar nodes there
     if (L.nfctiles > 0)
-      PROF_LAUNCH(s, PK_FACE2, st, (17 * cbf + 4 * cm + 5 * cbf) * w + 8 * cm,
-                  k_face2c<T><<<L.nfctiles, PMG_FACE_TILE, 0, st>>>(D, L.d_fcrec, W.qf, W.gf, W.Phi));
+      PROF_LAUNCH(s, PK_FACE2, st, (9 * cbf + 4 * cm + 5 * cbf) * w + 8 * cm,
+                  k_face2c<T><<<L.nfctiles, PMG_FACE_TILE, 0, st>>>(D, L.d_fcrec, W.qf, W.fvn, W.Phi));
     if (L.nf1tiles > 0)
       PROF_LAUNCH(s, PK_FACE2, st, (17 * ncf + 4 * (nm - cm) + 5 * ncf) * w,
                   k_face2<T><<<L.nf1tiles, PMG_FACE_TILE, 0, st>>>(D, L.d_f1list, W.qf, W.gf, W.Phi));
@@ -1505,10 +1514,10 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   const double w = prec == PREC_F32 ? 4.0 : 8.0;
   double b = 4.0 * (3 * K + (K + 1) + 6 * K + c.nn + c.nm + c.nm / 64.0 + 2) + sizeof(FaceRec) * c.nfaces;
   b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0) + 2 * c.nn);  // FP64 geometry
-  if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf);  // shared work arrays
+  if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf + 4 * c.nf);  // shared work arrays
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 3 * 4.0 * K + 32.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
-  b += 4.0 * c.nf + 16.0 * (c.nm / 64.0 + 2);  // interface-state links, face-tile list and records
+  b += 8.0 * c.nf + 16.0 * (c.nm / 64.0 + 2);  // interface links (state, mortar node), face-tile list and records
   b += 8.0 * std::max(c.nm, 1.0);              // face nodes of the conforming mortar nodes
   b += 4.0 * 2;                                // tile range of the problem
   b += (top ? 6.0 : 7.0) * 5 * c.nn * w;           // Q (not on top), Q0, S, r, Sp, G, R
