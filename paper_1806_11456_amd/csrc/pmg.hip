@@ -717,13 +717,14 @@ static void launch_trace(const Level& L, const LevelDevT<T>& D, const T* Q, T* q
 
 template <class T>
 static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const T* qf, const T* Ws, int isolated,
-                        T* gW, T* gf, T* fvn, hipStream_t st) {
+                        T* gW, T* gf, T* fvn, T* phi, hipStream_t st) {
   const size_t lds = L.lds_grad();
-  if (L.block == 64) k_grad<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn);
-  else if (L.block == 128) k_grad<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn);
+  if (L.block == 64) k_grad<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn, phi);
+  else if (L.block == 128)
+    k_grad<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn, phi);
   else if (L.max_tile <= PMG_BLOCK)
-    k_grad<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn);
-  else k_grad<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn);
+    k_grad<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn, phi);
+  else k_grad<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn, phi);
 }
 
 template <class T>
@@ -734,14 +735,6 @@ static void launch_div(const Level& L, const LevelDevT<T>& D, const T* Q, const 
   else if (L.block == 128) k_div<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, gW, Phi, a);
   else if (L.max_tile <= PMG_BLOCK) k_div<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, gW, Phi, a);
   else k_div<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, gW, Phi, a);
-}
-
-template <class T>
-static void launch_face2_iso(const Level& L, const LevelDevT<T>& D, const T* qf, const T* fvn, T* Phi,
-                             hipStream_t st) {
-  if (L.block == 64) k_face2_iso<T, 64><<<L.ntiles, 64, 0, st>>>(D, qf, fvn, Phi);
-  else if (L.block == 128) k_face2_iso<T, 128><<<L.ntiles, 128, 0, st>>>(D, qf, fvn, Phi);
-  else k_face2_iso<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, qf, fvn, Phi);
 }
 
 template <class T>
@@ -789,13 +782,11 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
   // face values of the gradient: the trace on mortar faces, F^v . n (own trace again, interface normal and
   // link) elsewhere
   const double wsrc = isolated ? 5 * nf : 10 * cf + 8 * bf + 4 * ncf + nf * 4.0 / w;
-  const double gout = isolated ? 5 * nf + 4 * nf : 12 * ncf + (cf + bf) * (5 + 3 + 4) + cf * 4.0 / w;
+  // (isolated: the flux itself from the own trace and N_out)
+  const double gout = isolated ? 5 * nf + 5 * nf : 12 * ncf + (cf + bf) * (5 + 3 + 4) + cf * 4.0 / w;
   PROF_LAUNCH(s, PK_GRAD, st, (15 * nn + 3 * nf + wsrc + 12 * nn + gout) * w,
-              launch_grad(L, D, Q, (const T*)W.qf, (const T*)W.Ws, isolated ? 1 : 0, W.gW, W.gf, W.fvn, st));
-  if (isolated) {
-    PROF_LAUNCH(s, PK_FACE2, st, (5 * nf + 4 * nf + 3 * nf + 5 * nf) * w,
-                launch_face2_iso(L, D, (const T*)W.qf, (const T*)W.fvn, W.Phi, st));
-  } else {
+              launch_grad(L, D, Q, (const T*)W.qf, (const T*)W.Ws, isolated ? 1 : 0, W.gW, W.gf, W.fvn, W.Phi, st));
+  if (!isolated) {
     // numerical flux: the flat pass on conforming and boundary faces, the mortar pass on the others
     const double cbf = cf + bf, cm = cf / 2 + bf;  // face nodes and mortar nodes there
     if (L.nfctiles > 0)
