@@ -312,6 +312,13 @@ pmg_status pmg_level_tiles(pmg_solver s, int hierarchy, int level, int32_t* tile
  */
 pmg_status pmg_profile_enable(pmg_solver s, uint32_t mask);
 pmg_status pmg_profile_read(pmg_solver s, int kind, double* total_ms, int64_t* launches, double* alg_bytes);
+/*
+ * Sample the timing: bracket only every stride-th launch of each selected kind (1, the default: every
+ * launch), counting from this call.  A stride coprime with the number of launches of a kind per repeated
+ * step samples every launch position of the step over `stride` steps, at 1/stride of the timing overhead.
+ * PMG_ERR_INVALID_ARG for stride < 1.
+ */
+pmg_status pmg_profile_stride(pmg_solver s, int32_t stride);
 
 #ifdef __cplusplus
 }

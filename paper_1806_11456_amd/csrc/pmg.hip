@@ -205,6 +205,8 @@ enum { PK_TRACE = 0, PK_FACE1 = 1, PK_GRAD = 2, PK_FACE2 = 3, PK_DIV = 4, PK_DT 
 
 struct Prof {
   uint32_t mask = 0;
+  int stride = 1;                 // time every stride-th launch of each selected kind
+  int64_t count[PK_N] = {0};      // launches of each kind seen while selected
   std::vector<hipEvent_t> pool;
   size_t next = 0;
   struct Rec {
@@ -218,6 +220,7 @@ struct Prof {
   }
   size_t begin(int kind, hipStream_t st) {
     if (!((mask >> kind) & 1u)) return SIZE_MAX;
+    if (count[kind]++ % stride != 0) return SIZE_MAX;
     while (pool.size() < next + 2) {
       hipEvent_t e;
       // device-scope release only: the timer does not need a system-wide fence around each kernel
@@ -2412,6 +2415,15 @@ pmg_status pmg_profile_enable(pmg_solver s, uint32_t mask) {
     REQUIRE(s, "NULL solver");
     REQUIRE((mask >> PK_N) == 0, "unknown kernel kind in mask");
     s->prof->mask = mask;
+  });
+}
+
+pmg_status pmg_profile_stride(pmg_solver s, int32_t stride) {
+  return guard([&] {
+    REQUIRE(s, "NULL solver");
+    REQUIRE(stride >= 1, "stride must be at least 1");
+    s->prof->stride = stride;
+    for (auto& c : s->prof->count) c = 0;
   });
 }
 

@@ -23,7 +23,7 @@ STATUS = {0: "PMG_OK", 1: "PMG_ERR_INVALID_ARG", 2: "PMG_ERR_OOM", 3: "PMG_ERR_H
 EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_create", "pmg_mesh_destroy",
            "pmg_solver_create", "pmg_solver_destroy", "pmg_state_layout", "pmg_init_freestream", "pmg_residual",
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
-           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_batch_create",
+           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_profile_stride", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
            "pmg_level_tiles", "pmg_solve_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
            "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy", "pmg_tau_nodal",
@@ -106,6 +106,7 @@ def lib():
     L.pmg_restore.argtypes = [P, C.c_char_p, V, V]
     L.pmg_profile_enable.argtypes = [P, C.c_uint32]
     L.pmg_profile_read.argtypes = [P, C.c_int, D, I64, D]
+    L.pmg_profile_stride.argtypes = [P, C.c_int32]
     L.pmg_batch_create.argtypes = [P, C.c_int, C.POINTER(C.c_void_p), C.POINTER(I32), C.POINTER(Physics),
                                    C.POINTER(MGParams), pp]
     L.pmg_batch_layout.argtypes = [P, I32, I64]
@@ -325,11 +326,12 @@ class Solver:
         _check(lib().pmg_solve_stats(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))))
         return out
 
-    def profile(self, kinds):
-        """Bracket every launch of the given kernel kinds with HIP events (empty = off)."""
+    def profile(self, kinds, stride: int = 1):
+        """Bracket every stride-th launch of the given kernel kinds with HIP events (empty = off)."""
         mask = 0
         for k in kinds:
             mask |= 1 << KINDS[k]
+        _check(lib().pmg_profile_stride(self.h, int(stride)))
         _check(lib().pmg_profile_enable(self.h, mask))
 
     def profile_read(self, kind: str):
