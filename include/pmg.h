@@ -320,6 +320,42 @@ pmg_status pmg_profile_read(pmg_solver s, int kind, double* total_ms, int64_t* l
  */
 pmg_status pmg_profile_stride(pmg_solver s, int32_t stride);
 
+/*
+ * Truncation-error-driven anisotropic p-adaptation (paper, Sec. 3.3.2; eq. AnisTruncError of Sec. 3.2.1; order
+ * jumps: eq. poljump2D of Sec. 4.1.2 and Sec. 4.2.1).  Host function: every pointer is a host pointer, no
+ * device or solver is needed.
+ *
+ * Inputs: the mesh connectivity as given to pmg_mesh_create (K elements; nbr_elem[K*6], nbr_face[K*6],
+ * orient[K*6], bc[K*6]); the reference orders P[K*3] (each 1..7) on which the map was estimated; the
+ * directional truncation-error map tau_map[K][3][nt] of pmg_tau_estimate (entry (e, d, n-1): the element's
+ * infinity norm of the truncation error with order n < P_d in direction d; NaN where not estimated).
+ *
+ * Per element: the inner map (orders n_min <= N_d < P_d, tau(N) = tau_1(N_1) + tau_2(N_2) + tau_3(N_3)) is
+ * searched for tau(N) < tau_max; failing that, each direction's values are extrapolated to
+ * P_d <= N_d <= n_max[d] by a least-squares fit of log tau_d(n) = a + b n over its measured orders (at least two
+ * positive values) and the full map is searched; among the combinations found, the fewest degrees of freedom
+ * (N1+1)(N2+1)(N3+1), ties broken by the lexicographically smallest triple; none: N_d = n_max[d].  A direction
+ * without estimates (P_d = 1) keeps P_d and adds nothing.  Then, with jump_rule 1 (|N_i+ - N_i-| <= 1) or 2
+ * (N_i+ >= floor(2 N_i- / 3)) and/or wall_conforming (elements that both touch a no-slip wall have equal orders
+ * across their common face), the lower side is raised, direction by direction through the face orientation,
+ * until every constraint holds (the least such orders).  The comparisons are taken in FP64 without fused
+ * multiply-adds.
+ *
+ * Output: new_orders[K*3] (caller-owned).  PMG_ERR_INVALID_ARG for NULL pointers, orders outside 1..7,
+ * n_max outside n_min..7, tau_max <= 0, an unknown jump rule.
+ */
+typedef struct {
+  double tau_max;
+  int32_t n_max[3];
+  int32_t n_min;
+  int32_t jump_rule;       /* 0 none, 1 |N+ - N-| <= 1, 2 N+ >= floor(2 N- / 3) */
+  int32_t wall_conforming; /* 1: equal orders across faces between elements that both touch a no-slip wall */
+} pmg_adapt_params;
+
+pmg_status pmg_adapt_orders(int64_t K, const int64_t* nbr_elem, const int32_t* nbr_face, const int32_t* orient,
+                            const int32_t* bc, const int32_t* orders, const double* tau_map, int32_t nt,
+                            const pmg_adapt_params* prm, int32_t* new_orders);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2436,3 +2436,5 @@ pmg_status pmg_profile_read(pmg_solver s, int kind, double* total_ms, int64_t* l
 }
 
 }  // extern "C"
+
+#include "adapt.inc"

@@ -23,7 +23,7 @@ STATUS = {0: "PMG_OK", 1: "PMG_ERR_INVALID_ARG", 2: "PMG_ERR_OOM", 3: "PMG_ERR_H
 EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_create", "pmg_mesh_destroy",
            "pmg_solver_create", "pmg_solver_destroy", "pmg_state_layout", "pmg_init_freestream", "pmg_residual",
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
-           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_profile_stride", "pmg_batch_create",
+           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_profile_stride", "pmg_adapt_orders", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
            "pmg_level_tiles", "pmg_solve_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
            "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy", "pmg_tau_nodal",
@@ -78,6 +78,9 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1806_11456_amd/build.py "
                            "(or __graft_entry__.build()); there is no fallback path")
+    # torch first: the library's HIP runtime dependency then resolves to the runtime torch already holds,
+    # so the process has one HIP runtime whichever call (host-only or device) loads the library first
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, D, I32, I64, V = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_void_p
     pp = C.POINTER(C.c_void_p)
@@ -107,6 +110,7 @@ def lib():
     L.pmg_profile_enable.argtypes = [P, C.c_uint32]
     L.pmg_profile_read.argtypes = [P, C.c_int, D, I64, D]
     L.pmg_profile_stride.argtypes = [P, C.c_int32]
+    L.pmg_adapt_orders.argtypes = [C.c_int64, I64, I32, I32, I32, I32, D, C.c_int32, C.POINTER(AdaptParams), I32]
     L.pmg_batch_create.argtypes = [P, C.c_int, C.POINTER(C.c_void_p), C.POINTER(I32), C.POINTER(Physics),
                                    C.POINTER(MGParams), pp]
     L.pmg_batch_layout.argtypes = [P, I32, I64]
@@ -205,6 +209,35 @@ def footprint(mesh: "Mesh", orders, mg: "MG" = None):
     _check(lib().pmg_footprint(mesh.h, orders.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(p), C.byref(b),
                                C.byref(t), C.byref(sw)))
     return int(b.value), int(t.value), int(sw.value)
+
+
+class AdaptParams(C.Structure):
+    _fields_ = [("tau_max", C.c_double), ("n_max", C.c_int32 * 3), ("n_min", C.c_int32), ("jump_rule", C.c_int32),
+                ("wall_conforming", C.c_int32)]
+
+
+def adapt_orders(mesh, orders, tau_map, tau_max: float, n_max=(7, 7, 7), n_min: int = 1, jump_rule: int = 1,
+                 wall_conforming: bool = False):
+    """New element orders (K, 3) from the reference orders and the directional truncation-error map
+    [K][3][nt] (pmg_adapt_orders: a host function; ``mesh`` is the host-side mesh description of
+    paper_1806_11456_amd.inputs)."""
+    K = int(mesh.K)
+    tau = np.ascontiguousarray(tau_map, dtype=np.float64)
+    assert tau.ndim == 3 and tau.shape[0] == K and tau.shape[1] == 3
+    nbr = np.ascontiguousarray(mesh.nbr_elem, dtype=np.int64)
+    nbf = np.ascontiguousarray(mesh.nbr_face, dtype=np.int32)
+    ori = np.ascontiguousarray(mesh.orient, dtype=np.int32)
+    bc = np.ascontiguousarray(mesh.bc, dtype=np.int32)
+    P = np.ascontiguousarray(orders, dtype=np.int32)
+    out = np.zeros((K, 3), dtype=np.int32)
+    prm = AdaptParams(float(tau_max), (C.c_int32 * 3)(*[int(v) for v in n_max]), int(n_min), int(jump_rule),
+                      int(bool(wall_conforming)))
+    i32, i64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    _check(lib().pmg_adapt_orders(K, nbr.ctypes.data_as(i64), nbf.ctypes.data_as(i32), ori.ctypes.data_as(i32),
+                                  bc.ctypes.data_as(i32), P.ctypes.data_as(i32),
+                                  tau.ctypes.data_as(C.POINTER(C.c_double)), int(tau.shape[2]), C.byref(prm),
+                                  out.ctypes.data_as(i32)))
+    return out
 
 
 def device_bytes() -> int:

@@ -1,0 +1,140 @@
+"""Pins of the p-adaptation oracle (CPU): what the selection and the order-jump rules must give, checked
+against closed forms, brute force and invariants rather than against the oracle's own formulas.
+
+* A map that follows tau_d(n) = C_d exp(-k_d n) exactly: the linear-log fit recovers the law, so the selected
+  orders equal an exhaustive search over the exact law (margins from tau_max checked).
+* The inner map wins when it can; the n_max fallback when nothing reaches tau_max; a direction without
+  estimates keeps its order; ties go to the lexicographically smallest triple.
+* After the jump rules every face satisfies them (directions matched through the mesh's published
+  orientation convention, not the oracle's), orders only rise, the result is a fixed point and it is the least
+  one (lowering any raised order breaks a constraint).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import adapt as A
+from paper_1806_11456_amd import inputs as I
+
+
+def law_map(P, C, k, nt):
+    tau = np.full((3, nt), np.nan)
+    for d in range(3):
+        for n in range(1, P[d]):
+            tau[d, n - 1] = C[d] * math.exp(-k[d] * n)
+    return tau
+
+
+def brute(P, C, k, tau_max, n_max, n_min, inner_only):
+    """Exhaustive search over the exact law (no fit), with the selection rule of the method."""
+    best = None
+    rng = [range(max(n_min, 1), P[d] if inner_only else n_max[d] + 1) if P[d] > 1 else [P[d]] for d in range(3)]
+    for N in itertools.product(*rng):
+        tau = sum(C[d] * math.exp(-k[d] * N[d]) for d in range(3) if P[d] > 1)
+        if tau < tau_max:
+            key = ((N[0] + 1) * (N[1] + 1) * (N[2] + 1),) + tuple(N)
+            best = key if best is None or key < best else best
+    return None if best is None else list(best[1:])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_exponential_law_is_recovered(seed):
+    rng = np.random.default_rng(seed)
+    P = [int(v) for v in rng.integers(3, 6, size=3)]
+    C = rng.uniform(0.5, 5.0, size=3)
+    k = rng.uniform(0.6, 2.0, size=3)
+    n_max = [7, 7, 7]
+    tau_e = law_map(P, C, k, 6)
+    for tau_max in np.geomspace(1e-5, 1.0, 13):
+        want = brute(P, C, k, tau_max, n_max, 1, True) or brute(P, C, k, tau_max, n_max, 1, False)
+        if want is None:
+            want = list(n_max)
+        # keep away from decision boundaries: every candidate's tau differs from tau_max by > 1e-9 relative
+        cands = itertools.product(*[range(1, 8)] * 3)
+        margin = min(abs(sum(C[d] * math.exp(-k[d] * N[d]) for d in range(3)) - tau_max) / tau_max for N in cands)
+        if margin < 1e-9:
+            continue
+        assert A.element_orders(P, tau_e, tau_max, n_max) == want, (P, tau_max)
+
+
+def test_inner_fallback_frozen_and_ties():
+    # inner: generous tau_max -> the lowest orders everywhere
+    tau_e = law_map([5, 4, 1], [1.0, 1.0, 1.0], [1.0, 1.0, 1.0], 6)
+    assert A.element_orders([5, 4, 1], tau_e, 10.0, [7, 7, 7]) == [1, 1, 1]
+    # n_max fallback in the estimated directions; z (P = 1, nothing estimated) keeps its order
+    assert A.element_orders([5, 4, 1], tau_e, 1e-30, [7, 6, 7]) == [7, 6, 1]
+    # n_min restricts the candidates
+    assert A.element_orders([5, 4, 1], tau_e, 10.0, [7, 7, 7], n_min=2) == [2, 2, 1]
+    # tie in degrees of freedom between (1, 2, 1) and (2, 1, 1): the lexicographically smallest
+    tau_e = np.full((3, 6), np.nan)
+    tau_e[0, :3] = [0.5, 0.2, 0.1]
+    tau_e[1, :3] = [0.5, 0.2, 0.1]
+    assert A.element_orders([4, 4, 1], tau_e, 0.71, [7, 7, 7]) == [1, 2, 1]
+    # a single measurement cannot be extrapolated: the fallback
+    tau_e = np.full((3, 6), np.nan)
+    tau_e[0, 0] = 1.0
+    assert A.element_orders([2, 1, 1], tau_e, 0.5, [6, 6, 6]) == [6, 1, 1]
+
+
+def neighbour_axes(o, f, h):
+    """Directions matched across face f -> h from the published orientation convention (orient_map):
+    which of the neighbour's face coordinates our s and t axes become."""
+    d, dg = f // 2, h // 2
+    ta, tb = I.TANGENTIAL[d], I.TANGENTIAL[dg]
+    s0 = I.orient_map(o, 0.0, 0.0)
+    s1 = I.orient_map(o, 1.0, 0.0)
+    first = tb[0] if abs(s1[0] - s0[0]) > 0.5 else tb[1]
+    second = tb[1] if first == tb[0] else tb[0]
+    return [(d, dg), (ta[0], first), (ta[1], second)]
+
+
+def constraints_hold(mesh, N, rule, wall_conf):
+    wall = [any(mesh.bc[e, f] == I.BC_WALL and mesh.nbr_elem[e, f] < 0 for f in range(6)) for e in range(mesh.K)]
+    for e in range(mesh.K):
+        for f in range(6):
+            g = int(mesh.nbr_elem[e, f])
+            if g < 0:
+                continue
+            for i, j in neighbour_axes(int(mesh.orient[e, f]), f, int(mesh.nbr_face[e, f])):
+                a, b = int(N[e, i]), int(N[g, j])
+                if rule == 1 and abs(a - b) > 1:
+                    return False
+                if rule == 2 and (a < (2 * b) // 3 or b < (2 * a) // 3):
+                    return False
+                if wall_conf and wall[e] and wall[g] and a != b:
+                    return False
+    return True
+
+
+@pytest.mark.parametrize("rule,wall_conf", [(1, False), (2, False), (1, True)])
+def test_jump_rules_on_rotated_mesh(rule, wall_conf):
+    # periodic in x, a no-slip wall at z = -1, far field elsewhere; random element frames (orientation codes)
+    base = I.box_mesh((3, 3, 2), (-1, -1, -1), (1, 1, 1), M=(1, 1, 1), periodic=(True, False, False),
+                      bc_lo=(I.BC_FARFIELD, I.BC_FARFIELD, I.BC_WALL))
+    mesh, _ = I.reorient(base, 31, period=(2.0, None, None))
+    assert (mesh.orient != 0).any()
+    rng = np.random.default_rng(5)
+    N0 = rng.integers(1, 8, size=(mesh.K, 3))
+    N = A.enforce_jumps(mesh, N0, rule, wall_conf)
+    assert constraints_hold(mesh, N, rule, wall_conf)
+    assert (N >= N0).all()
+    assert (A.enforce_jumps(mesh, N, rule, wall_conf) == N).all()
+    # least fixed point: no raised order can be lowered by one
+    for e, d in zip(*np.nonzero(N > N0)):
+        M = N.copy()
+        M[e, d] -= 1
+        assert not constraints_hold(mesh, M, rule, wall_conf), (e, d)
+
+
+def test_adapt_orders_plate_map_shape():
+    wl = I.config_plate(8, 4)
+    K = wl.mesh.K
+    rng = np.random.default_rng(2)
+    tau = np.full((K, 3, 5), np.nan)
+    tau[:, 0, :5] = rng.uniform(1e-4, 1e-1, size=(K, 5))
+    tau[:, 1, :5] = rng.uniform(1e-4, 1e-1, size=(K, 5))
+    N = A.adapt_orders(wl.mesh, wl.orders, tau, 1e-2, (7, 7, 7), rule=1)
+    assert N.shape == (K, 3) and (N[:, 2] == wl.orders[:, 2]).all()
+    assert constraints_hold(wl.mesh, N, 1, False)
