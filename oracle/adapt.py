@@ -23,6 +23,13 @@ Afterwards the order-jump rule between face neighbours is enforced by raising th
 changes (a monotone fixed point, so the order of the sweeps does not matter), direction by direction through
 the face orientation: rule 1, |N_i^+ - N_i^-| <= 1; rule 2, N_i^+ >= floor(2/3 N_i^-).  Optionally elements
 that both touch a no-slip wall are made conforming across their common face (equal orders, the larger).
+
+Multi-stage adaptation inside the FMG cycle (Sec. 3.3.4): stages at increasing orders P_1 < P_2 < ...; the
+problem is converged at the current orders, its map estimated by the 3V cycle and the orders selected as above
+but never above the next stage's order (the cap is applied before the jump rule); the adaptation ends at the
+stage whose largest required order (before the cap) does not exceed the next stage's order, or at the last
+stage.  The state follows every change of orders (per direction: interpolation up, L2 projection down), then
+the adapted problem is solved to the final tolerance.
 """
 from __future__ import annotations
 
@@ -144,12 +151,55 @@ def enforce_jumps(mesh, N, rule, wall_conforming=False):
     return N
 
 
-def adapt_orders(mesh, orders, tau_map, tau_max, n_max, n_min=1, rule=1, wall_conforming=False):
-    """New orders (K, 3) from the reference orders (K, 3) and the directional tau map [K][3][nt]."""
+def select_orders(mesh, orders, tau_map, tau_max, n_max, n_min=1, rule=1, wall_conforming=False, cap=None):
+    """(new orders (K, 3), largest selected order before the cap) from the reference orders (K, 3) and the
+    directional tau map [K][3][nt]; 'cap' (a stage's upper order) bounds the selection in every direction with
+    estimates before the jump rule is enforced."""
     K = mesh.K
     out = np.zeros((K, 3), dtype=np.int64)
     for e in range(K):
         out[e] = element_orders([int(v) for v in orders[e]], tau_map[e], tau_max, list(n_max), n_min)
+    max_required = int(out.max())
+    if cap is not None:
+        for e in range(K):
+            for d in range(3):
+                if out[e, d] > cap:
+                    out[e, d] = cap
     if rule or wall_conforming:
         out = enforce_jumps(mesh, out, rule, wall_conforming)
-    return out
+    return out, max_required
+
+
+def adapt_orders(mesh, orders, tau_map, tau_max, n_max, n_min=1, rule=1, wall_conforming=False, cap=None):
+    """New orders (K, 3) (see select_orders)."""
+    return select_orders(mesh, orders, tau_map, tau_max, n_max, n_min, rule, wall_conforming, cap)[0]
+
+
+def multistage(ora, mesh, orders, stages, tau_max, n_max, n_min=1, rule=1, wall_conforming=False, conv=0.1,
+               final_tol=1e-8, max_cycles=100, Q0=None, **mg):
+    """Multi-stage adaptation from the first stage's orders, with the oracle's solver ('ora', an
+    oracle.Oracle on 'mesh'); 'mg' are the multigrid parameters (the first solve may start with FMG, later
+    ones continue V-cycling from the carried-over state).  Returns (orders, Q, reports, final cycles, final
+    residual); a report per stage: dict(order, cycles, res, dof_before, dof_after, max_required, last)."""
+    N = np.asarray(orders, dtype=np.int64).copy()
+    Q = np.array(Q0, dtype=np.float64, copy=True)
+    reports = []
+    for i, P in enumerate(stages):
+        prm = dict(mg)
+        if i > 0:
+            prm["fmg"] = 0
+        Q, cyc, res, _ = ora.solve(N, Q, None, tol=conv * tau_max, max_cycles=max_cycles, **prm)
+        tau, Q = ora.tau_3v(N, Q, None, **dict(prm, isolated=1))
+        nxt = stages[i + 1] if i + 1 < len(stages) else None
+        M, req = select_orders(mesh, N, tau, tau_max, n_max, n_min, rule, wall_conforming, nxt)
+        last = nxt is None or req <= nxt
+        dof0 = int(np.prod(N + 1, axis=1).sum())
+        Q = ora.remap(N, M, Q)
+        reports.append(dict(order=int(P), cycles=cyc, res=res, dof_before=dof0,
+                            dof_after=int(np.prod(M + 1, axis=1).sum()), max_required=req, last=bool(last)))
+        N = M
+        if last:
+            break
+    prm = dict(mg, fmg=0)
+    Q, cyc, res, _ = ora.solve(N, Q, None, tol=final_tol, max_cycles=max_cycles, **prm)
+    return N, Q, reports, cyc, res

@@ -107,7 +107,8 @@ void ora_smooth(or_problem* P, const int32_t* ord, double* Q, const double* S, i
 void ora_transfer(or_problem* P, const int32_t* ord_from, const int32_t* ord_to, int prolong, const double* U, double* V) {
   or_level* A = or_level_create(P, ord_from);
   or_level* B = or_level_create(P, ord_to);
-  if (prolong) or_prolong(P, A, B, U, V);
+  if (prolong == 2) or_remap(P, A, B, U, V);
+  else if (prolong) or_prolong(P, A, B, U, V);
   else or_restrict(P, A, B, U, V);
   or_level_destroy(A);
   or_level_destroy(B);

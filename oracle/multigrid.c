@@ -76,7 +76,9 @@ void or_smooth(const or_problem* P, const or_level* L, double* Q, const double* 
 }
 
 /* Tensor-product transfer of an nvar-field between two order tensors on the same mesh.
- * prolong = 0: L2 projection (fine -> coarse); prolong = 1: interpolation (coarse -> fine). */
+ * prolong = 0: L2 projection (fine -> coarse); prolong = 1: interpolation (coarse -> fine);
+ * prolong = 2: direction by direction, interpolation where the order rises and L2 projection where it falls
+ * (the state carried over to the new orders after an adaptation, Sec. 3.3). */
 static void transfer(const or_problem* P, const or_level* Lfrom, const or_level* Lto, const double* U, double* V,
                      int nvar, int prolong) {
   for (int64_t e = 0; e < Lfrom->K; e++) {
@@ -89,7 +91,7 @@ static void transfer(const or_problem* P, const or_level* Lfrom, const or_level*
       if (a[d] == b[d]) {
         for (int i = 0; i < b[d]; i++)
           for (int j = 0; j < a[d]; j++) T[d][i * a[d] + j] = (i == j) ? 1.0 : 0.0;
-      } else if (prolong) {
+      } else if (prolong == 1 || (prolong == 2 && b[d] > a[d])) {
         or_interp_matrix(bf, bt->x, bt->n, T[d]); /* T[to][from] = l_from(x_to) */
       } else {
         or_projection_matrix(bt, bf, T[d]);       /* R[coarse][fine] */
@@ -116,6 +118,9 @@ void or_restrict(const or_problem* P, const or_level* Lf, const or_level* Lc, co
 }
 void or_prolong(const or_problem* P, const or_level* Lc, const or_level* Lf, const double* Uc, double* Uf) {
   transfer(P, Lc, Lf, Uc, Uf, 5, 1);
+}
+void or_remap(const or_problem* P, const or_level* La, const or_level* Lb, const double* Ua, double* Ub) {
+  transfer(P, La, Lb, Ua, Ub, 5, 2);
 }
 
 /* ---------------------------------------------------------------------------------------------------- */

@@ -230,6 +230,16 @@ class Oracle:
         lib().ora_transfer(self.h, _i32(self._ord(ord_from)), _i32(self._ord(ord_to)), int(prolong), _d(U), _d(V))
         return V
 
+    def remap(self, ord_from, ord_to, U):
+        """State on new orders (after an adaptation): per element and direction, interpolation where the order
+        rises, L2 projection where it falls."""
+        U = _f64(U)
+        nn, _ = self.sizes(ord_to)
+        V = np.zeros((U.shape[0], nn))
+        assert U.shape[0] == 5
+        lib().ora_transfer(self.h, _i32(self._ord(ord_from)), _i32(self._ord(ord_to)), 2, _d(U), _d(V))
+        return V
+
     def vcycles(self, orders, Q, S=None, caps=None, ncycles=1, dir=-1, **prm):
         orders = self._ord(orders)
         if caps is None:

@@ -30,6 +30,8 @@ double or_norm_inf(const double* R, int64_t n);
 void or_smooth(const or_problem* P, const or_level* L, double* Q, const double* S, int sweeps);
 void or_restrict(const or_problem* P, const or_level* Lf, const or_level* Lc, const double* Uf, double* Uc);
 void or_prolong(const or_problem* P, const or_level* Lc, const or_level* Lf, const double* Uc, double* Uf);
+/* per direction: interpolation where the order rises, L2 projection where it falls */
+void or_remap(const or_problem* P, const or_level* La, const or_level* Lb, const double* Ua, double* Ub);
 or_mg* or_mg_create(const or_problem* P, const int32_t* ord, int nlev, const int* caps, int aniso_dir);
 void or_mg_destroy(or_mg* mg);
 double or_mg_vcycles(const or_problem* P, or_mg* mg, double* Q, const double* S, int ncycles, const or_mg_params* prm,

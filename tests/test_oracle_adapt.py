@@ -138,3 +138,98 @@ def test_adapt_orders_plate_map_shape():
     N = A.adapt_orders(wl.mesh, wl.orders, tau, 1e-2, (7, 7, 7), rule=1)
     assert N.shape == (K, 3) and (N[:, 2] == wl.orders[:, 2]).all()
     assert constraints_hold(wl.mesh, N, 1, False)
+
+
+# ---- state carried over to new orders, and the multi-stage driver ------------------------------------------
+
+def _oracle(wl):
+    from oracle import oracle as O
+    return O.Oracle(wl.mesh, wl.phys)
+
+
+def test_remap_is_projection_then_interpolation():
+    """Per direction the carry-over interpolates where the order rises and projects where it falls; the
+    operators of different directions commute, so it equals the pure L2 projection to the common lower orders
+    followed by the pure interpolation (both pinned on their own) to the new orders."""
+    wl = I.config_box(n=2, N=3)
+    o = _oracle(wl)
+    rng = np.random.default_rng(3)
+    A = rng.integers(1, 8, size=(wl.mesh.K, 3))
+    B = rng.integers(1, 8, size=(wl.mesh.K, 3))
+    assert ((A > B).any(axis=1) & (A < B).any(axis=1)).any()  # mixed rises and falls inside one element
+    U = rng.uniform(-1, 1, size=(5, int(np.prod(A + 1, axis=1).sum())))
+    Cm = np.minimum(A, B)
+    want = o.transfer(Cm, B, o.transfer(A, Cm, U, prolong=False), prolong=True)
+    got = o.remap(A, B, U)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(U).max()
+
+
+def test_remap_reproduces_polynomials():
+    """A tensor polynomial of degree <= min(A_d, B_d) per direction is carried over exactly (Gauss nodes from
+    numpy's Gauss-Legendre routine, node i fastest, then j, then k)."""
+    wl = I.config_plate(2, 2)  # Gauss nodes
+    o = _oracle(wl)
+    rng = np.random.default_rng(4)
+    K = wl.mesh.K
+    A = rng.integers(1, 8, size=(K, 3))
+    B = rng.integers(1, 8, size=(K, 3))
+
+    def field(orders, coef):
+        out = []
+        for e in range(K):
+            x = [np.polynomial.legendre.leggauss(int(orders[e, d]) + 1)[0] for d in range(3)]
+            vals = [np.polynomial.polynomial.polyval(x[d], coef[e][d]) for d in range(3)]
+            out.append(np.einsum("k,j,i->kji", vals[2], vals[1], vals[0]).ravel())
+        return np.concatenate(out)
+
+    coef = [[rng.uniform(-1, 1, size=min(A[e, d], B[e, d]) + 1) for d in range(3)] for e in range(K)]
+    U = np.stack([field(A, coef) * (v + 1) for v in range(5)])
+    V = np.stack([field(B, coef) * (v + 1) for v in range(5)])
+    assert np.abs(o.remap(A, B, U) - V).max() <= 1e-12 * np.abs(V).max()
+
+
+def test_selection_cap_before_jump_rule():
+    """The stage cap bounds the selection before the jump rule: a capped element lifts its neighbour only to
+    cap - 1 (rule 1), and the largest required order is the uncapped selection's."""
+    mesh = I.box_mesh((2, 1, 1), (0, 0, 0), (2, 1, 1), M=(1, 1, 1))
+    orders = np.array([[3, 3, 3], [3, 3, 3]])
+    tau = np.full((2, 3, 2), np.nan)
+    tau[0] = 1.0        # nothing reaches tau_max: fallback to n_max
+    tau[1] = 1e-9       # everything does: the lowest orders
+    N, req = A.select_orders(mesh, orders, tau, 1e-3, (7, 7, 7), 1, 1, False, cap=4)
+    assert req == 7
+    assert N.tolist() == [[4, 4, 4], [3, 3, 3]]
+    N, _ = A.select_orders(mesh, orders, tau, 1e-3, (7, 7, 7), 1, 1, False)
+    assert N.tolist() == [[7, 7, 7], [6, 6, 6]]
+
+
+def test_multistage_freestream_ends_at_lowest_orders():
+    """Free stream on the Lobatto box (preserved to round-off): every truncation error vanishes, so the first
+    stage selects n_min everywhere, the required order does not exceed the next stage and the adaptation ends
+    there with the free stream carried over exactly."""
+    wl = I.config_box(n=2, N=3)
+    o = _oracle(wl)
+    nn = int(np.prod(wl.orders + 1, axis=1).sum())
+    Q0 = I.freestream_state(nn, wl.phys.mach)
+    N, Q, rep, cyc, res = A.multistage(o, wl.mesh, wl.orders, (3, 5), 1e-6, (7, 7, 7), n_min=1, conv=0.1,
+                                       final_tol=1e-10, max_cycles=2, Q0=Q0, beta_pre=1, beta_post=1,
+                                       beta_coarse=2, fmg=1)
+    assert (N == 1).all() and len(rep) == 1 and rep[0]["last"] and rep[0]["max_required"] == 1
+    assert rep[0]["dof_after"] == 8 * wl.mesh.K
+    assert np.abs(Q - I.freestream_state(8 * wl.mesh.K, wl.phys.mach)).max() <= 1e-12 * np.abs(Q0).max()
+
+
+def test_multistage_stage_caps():
+    """Nothing reaches a vanishing tau_max: each stage falls back to n_max, capped at the next stage's order,
+    so the orders climb stage by stage, and the last stage lifts them to n_max."""
+    wl = I.config_box(n=2, N=2)
+    o = _oracle(wl)
+    N, Q, rep, cyc, res = A.multistage(o, wl.mesh, wl.orders, (2, 3, 4), 1e-30, (5, 5, 5), conv=0.1,
+                                       final_tol=1e-30, max_cycles=1, Q0=wl.Q, beta_pre=1, beta_post=1,
+                                       beta_coarse=1)
+    K = wl.mesh.K
+    assert (N == 5).all()
+    assert [r["dof_after"] for r in rep] == [64 * K, 125 * K, 216 * K]  # (3+1)^3, (4+1)^3, (5+1)^3 nodes
+    assert [r["last"] for r in rep] == [False, False, True]
+    assert [r["max_required"] for r in rep] == [5, 5, 5]
+    assert Q.shape == (5, 216 * K) and np.isfinite(Q).all()
