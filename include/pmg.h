@@ -339,10 +339,12 @@ pmg_status pmg_profile_stride(pmg_solver s, int32_t stride);
  * (N_i+ >= floor(2 N_i- / 3)) and/or wall_conforming (elements that both touch a no-slip wall have equal orders
  * across their common face), the lower side is raised, direction by direction through the face orientation,
  * until every constraint holds (the least such orders).  The comparisons are taken in FP64 without fused
- * multiply-adds.
+ * multiply-adds.  With n_cap > 0 (a multi-stage adaptation's next stage order, Sec. 3.3.4) every selected order
+ * above n_cap becomes n_cap before the jump rule is enforced.
  *
- * Output: new_orders[K*3] (caller-owned).  PMG_ERR_INVALID_ARG for NULL pointers, orders outside 1..7,
- * n_max outside n_min..7, tau_max <= 0, an unknown jump rule.
+ * Output: new_orders[K*3] (caller-owned); max_required (nullable): the largest selected order before the cap.
+ * PMG_ERR_INVALID_ARG for NULL pointers, orders outside 1..7, n_max outside n_min..7, tau_max <= 0, an unknown
+ * jump rule, 0 < n_cap < n_min.
  */
 typedef struct {
   double tau_max;
@@ -350,11 +352,69 @@ typedef struct {
   int32_t n_min;
   int32_t jump_rule;       /* 0 none, 1 |N+ - N-| <= 1, 2 N+ >= floor(2 N- / 3) */
   int32_t wall_conforming; /* 1: equal orders across faces between elements that both touch a no-slip wall */
+  int32_t n_cap;           /* > 0: upper bound on the selected orders (the next stage's order); 0: none */
 } pmg_adapt_params;
 
 pmg_status pmg_adapt_orders(int64_t K, const int64_t* nbr_elem, const int32_t* nbr_face, const int32_t* orient,
                             const int32_t* bc, const int32_t* orders, const double* tau_map, int32_t nt,
-                            const pmg_adapt_params* prm, int32_t* new_orders);
+                            const pmg_adapt_params* prm, int32_t* new_orders, int32_t* max_required);
+
+/*
+ * State carried over to new orders after an adaptation (Sec. 3.3.4: the solution continues on the adapted
+ * orders).  Per element and direction: exact interpolation where the order rises (the prolongation of
+ * eq. FASCorrectSol), the L2 projection of the restriction (eq. FASCoarseSol, Sec. 3.1) where it falls, the
+ * identity where it is unchanged;
+ * tensor product over the three directions.  Both solvers hold one problem each, on the same mesh handle and
+ * node family.  Q_from_dev [5][nn_from] and Q_to_dev [5][nn_to]: device, FP64, caller-owned, layouts of
+ * pmg_state_layout.  Enqueued on 'stream'; returns once it has completed.
+ */
+pmg_status pmg_remap_state(pmg_solver from, const double* Q_from_dev, pmg_solver to, double* Q_to_dev,
+                           void* stream);
+
+/*
+ * Multi-stage adaptation inside the FMG cycle (Sec. 3.3.4; each stage as in Sec. 3.3.2).  From free stream on
+ * the first stage's orders 'orders' [K*3] (host): for each stage i the problem (no physical source) is solved
+ * to max |r| < conv * tau_max (FMG start on the first stage if mg->fmg, V-cycles from the carried-over state
+ * afterwards; at most max_cycles), the isolated truncation-error map is estimated by the anisotropic 3V cycle
+ * and the orders are selected by pmg_adapt_orders with n_cap = stages[i+1] (none on the last stage); the state
+ * is carried over (pmg_remap_state).  The adaptation ends at the last stage or at the first one whose largest
+ * required order does not exceed stages[i+1]; the adapted problem is then solved to max |r| < final_tol.
+ * Every solver and buffer of the stages is the library's and is freed before the call returns.
+ *
+ * mg: multigrid parameters of every stage's solver (level_caps must be NULL: the levels follow the orders).
+ * Outputs (caller-owned): Q_out_dev (device) receives the final state as [5][nn] in its first 5*nn doubles,
+ * with nn <= capacity_nodes; out_orders[K*3], out_nodes (= nn), reports[n_stages] of which *n_reports are
+ * written, final_cycles and final_res (nullable).  PMG_ERR_NOT_CONVERGED when the final solve stops at
+ * max_cycles (every output written); a stage that stops there is reported (converged = 0) and the adaptation
+ * continues.  PMG_ERR_INVALID_ARG for bad parameters or a capacity below the adapted node count (out_nodes
+ * then holds the count needed).
+ */
+typedef struct {
+  const int32_t* stages;   /* host, n_stages increasing orders P_1 < P_2 < ... */
+  int32_t n_stages;
+  pmg_adapt_params adapt;  /* tau_max, n_max, n_min, jump rule, wall conformity; n_cap is set per stage */
+  double conv;             /* each stage is converged to conv * tau_max before its estimate (0.1) */
+  double final_tol;        /* tolerance of the final solve on the adapted orders */
+  int32_t max_cycles;      /* cap on the V-cycles of each solve */
+} pmg_multistage_params;
+
+typedef struct {
+  int32_t stage_order;     /* P_i */
+  int32_t cycles;          /* V-cycles of the solve before the estimate */
+  double res_inf;          /* max |r| when the estimate was taken */
+  int32_t converged;       /* 1: res_inf < conv * tau_max */
+  int32_t max_required;    /* largest selected order before the stage cap */
+  int32_t last;            /* 1: this stage ended the adaptation */
+  int32_t pad;
+  int64_t nodes_before;    /* nodes (degrees of freedom per variable) before and after the stage's adaptation */
+  int64_t nodes_after;
+} pmg_stage_report;
+
+pmg_status pmg_adapt_multistage(pmg_ctx ctx, pmg_mesh mesh, const int32_t* orders, const pmg_physics* phys,
+                                const pmg_mg_params* mg, const pmg_multistage_params* prm, double* Q_out_dev,
+                                int64_t capacity_nodes, int32_t* out_orders, int64_t* out_nodes,
+                                pmg_stage_report* reports, int32_t* n_reports, int32_t* final_cycles,
+                                double* final_res, void* stream);
 
 #ifdef __cplusplus
 }

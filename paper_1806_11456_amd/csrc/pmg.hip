@@ -667,9 +667,11 @@ static std::unique_ptr<XferTiles> build_xfer(const pmg_solver_s* s, const Level&
   int stride = 1;
   for (auto& kv : buckets) {
     int a = std::get<1>(kv.first), b = std::get<2>(kv.first);
-    int na = (a & 255) * ((a >> 8) & 255) * (a >> 16);
-    int nb = (b & 255) * ((b >> 8) & 255) * (b >> 16);
-    int big = std::max(na, nb);
+    const int a0 = a & 255, a1 = (a >> 8) & 255, a2 = a >> 16, b0 = b & 255, b1 = (b >> 8) & 255, b2 = b >> 16;
+    const int na = a0 * a1 * a2, nb = b0 * b1 * b2;
+    // largest stage of either sweep's tensor product (an order that rises in one direction and falls in
+    // another can exceed both ends; between levels of one hierarchy it is max(na, nb))
+    const int big = std::max({na, nb, b0 * a1 * a2, b0 * b1 * a2, a0 * b1 * b2, a0 * a1 * b2});
     int per = std::max(1, 256 / big);
     const auto& es = kv.second;
     for (size_t i = 0; i < es.size(); i += per) {

@@ -23,7 +23,8 @@ STATUS = {0: "PMG_OK", 1: "PMG_ERR_INVALID_ARG", 2: "PMG_ERR_OOM", 3: "PMG_ERR_H
 EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_create", "pmg_mesh_destroy",
            "pmg_solver_create", "pmg_solver_destroy", "pmg_state_layout", "pmg_init_freestream", "pmg_residual",
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
-           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_profile_stride", "pmg_adapt_orders", "pmg_batch_create",
+           "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_profile_stride", "pmg_adapt_orders",
+           "pmg_remap_state", "pmg_adapt_multistage", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
            "pmg_level_tiles", "pmg_solve_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
            "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy", "pmg_tau_nodal",
@@ -110,7 +111,12 @@ def lib():
     L.pmg_profile_enable.argtypes = [P, C.c_uint32]
     L.pmg_profile_read.argtypes = [P, C.c_int, D, I64, D]
     L.pmg_profile_stride.argtypes = [P, C.c_int32]
-    L.pmg_adapt_orders.argtypes = [C.c_int64, I64, I32, I32, I32, I32, D, C.c_int32, C.POINTER(AdaptParams), I32]
+    L.pmg_adapt_orders.argtypes = [C.c_int64, I64, I32, I32, I32, I32, D, C.c_int32, C.POINTER(AdaptParams), I32,
+                                   I32]
+    L.pmg_remap_state.argtypes = [P, V, P, V, V]
+    L.pmg_adapt_multistage.argtypes = [P, P, I32, C.POINTER(Physics), C.POINTER(MGParams),
+                                       C.POINTER(MultistageParams), V, C.c_int64, I32, I64,
+                                       C.POINTER(StageReport), I32, I32, D, V]
     L.pmg_batch_create.argtypes = [P, C.c_int, C.POINTER(C.c_void_p), C.POINTER(I32), C.POINTER(Physics),
                                    C.POINTER(MGParams), pp]
     L.pmg_batch_layout.argtypes = [P, I32, I64]
@@ -213,14 +219,25 @@ def footprint(mesh: "Mesh", orders, mg: "MG" = None):
 
 class AdaptParams(C.Structure):
     _fields_ = [("tau_max", C.c_double), ("n_max", C.c_int32 * 3), ("n_min", C.c_int32), ("jump_rule", C.c_int32),
-                ("wall_conforming", C.c_int32)]
+                ("wall_conforming", C.c_int32), ("n_cap", C.c_int32)]
+
+
+class MultistageParams(C.Structure):
+    _fields_ = [("stages", C.POINTER(C.c_int32)), ("n_stages", C.c_int32), ("adapt", AdaptParams),
+                ("conv", C.c_double), ("final_tol", C.c_double), ("max_cycles", C.c_int32)]
+
+
+class StageReport(C.Structure):
+    _fields_ = [("stage_order", C.c_int32), ("cycles", C.c_int32), ("res_inf", C.c_double),
+                ("converged", C.c_int32), ("max_required", C.c_int32), ("last", C.c_int32), ("pad", C.c_int32),
+                ("nodes_before", C.c_int64), ("nodes_after", C.c_int64)]
 
 
 def adapt_orders(mesh, orders, tau_map, tau_max: float, n_max=(7, 7, 7), n_min: int = 1, jump_rule: int = 1,
-                 wall_conforming: bool = False):
+                 wall_conforming: bool = False, n_cap: int = 0, with_required: bool = False):
     """New element orders (K, 3) from the reference orders and the directional truncation-error map
     [K][3][nt] (pmg_adapt_orders: a host function; ``mesh`` is the host-side mesh description of
-    paper_1806_11456_amd.inputs)."""
+    paper_1806_11456_amd.inputs); with ``with_required`` also the largest order selected before the cap."""
     K = int(mesh.K)
     tau = np.ascontiguousarray(tau_map, dtype=np.float64)
     assert tau.ndim == 3 and tau.shape[0] == K and tau.shape[1] == 3
@@ -230,14 +247,59 @@ def adapt_orders(mesh, orders, tau_map, tau_max: float, n_max=(7, 7, 7), n_min: 
     bc = np.ascontiguousarray(mesh.bc, dtype=np.int32)
     P = np.ascontiguousarray(orders, dtype=np.int32)
     out = np.zeros((K, 3), dtype=np.int32)
-    prm = AdaptParams(float(tau_max), (C.c_int32 * 3)(*[int(v) for v in n_max]), int(n_min), int(jump_rule),
-                      int(bool(wall_conforming)))
+    prm = adapt_params(tau_max, n_max, n_min, jump_rule, wall_conforming, n_cap)
     i32, i64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    req = C.c_int32()
     _check(lib().pmg_adapt_orders(K, nbr.ctypes.data_as(i64), nbf.ctypes.data_as(i32), ori.ctypes.data_as(i32),
                                   bc.ctypes.data_as(i32), P.ctypes.data_as(i32),
                                   tau.ctypes.data_as(C.POINTER(C.c_double)), int(tau.shape[2]), C.byref(prm),
-                                  out.ctypes.data_as(i32)))
-    return out
+                                  out.ctypes.data_as(i32), C.byref(req)))
+    return (out, int(req.value)) if with_required else out
+
+
+def adapt_params(tau_max, n_max=(7, 7, 7), n_min=1, jump_rule=1, wall_conforming=False, n_cap=0) -> AdaptParams:
+    return AdaptParams(float(tau_max), (C.c_int32 * 3)(*[int(v) for v in n_max]), int(n_min), int(jump_rule),
+                       int(bool(wall_conforming)), int(n_cap))
+
+
+def remap_state(src: "Solver", Q_src, dst: "Solver", Q_dst=None):
+    """The state of ``src`` carried over to the orders of ``dst`` (pmg_remap_state); returns Q_dst."""
+    Q_dst = dst.empty() if Q_dst is None else Q_dst
+    _check(lib().pmg_remap_state(src.h, _ptr(Q_src), dst.h, _ptr(Q_dst), _stream()))
+    return Q_dst
+
+
+def adapt_multistage(ctx: "Context", mesh: "Mesh", orders, phys, mg: "MG", stages, tau_max: float,
+                     n_max=(7, 7, 7), n_min: int = 1, jump_rule: int = 1, wall_conforming: bool = False,
+                     conv: float = 0.1, final_tol: float = 1e-8, max_cycles: int = 100,
+                     raise_not_converged: bool = True):
+    """Multi-stage adaptation from free stream on the first stage's ``orders`` (pmg_adapt_multistage).
+    Returns (orders (K, 3), state [5][nn] as a torch tensor, per-stage reports, final cycles, final residual)."""
+    import torch
+    K = int(mesh.K)
+    orders = np.ascontiguousarray(orders, dtype=np.int32)
+    st = np.ascontiguousarray(stages, dtype=np.int32)
+    top = [max(int(n_max[d]), int(orders[:, d].max())) + 1 for d in range(3)]
+    cap = K * top[0] * top[1] * top[2]
+    Q = torch.empty(5 * cap, dtype=torch.float64, device=torch.device("cuda", ctx.device))
+    p, caps_keep = mg_struct(mg)
+    ph = physics_struct(phys)
+    prm = MultistageParams(st.ctypes.data_as(C.POINTER(C.c_int32)), len(st),
+                           adapt_params(tau_max, n_max, n_min, jump_rule, wall_conforming, 0), float(conv),
+                           float(final_tol), int(max_cycles))
+    out = np.zeros((K, 3), dtype=np.int32)
+    nn = C.c_int64()
+    reps = (StageReport * len(st))()
+    nrep, cyc, res = C.c_int32(), C.c_int32(), C.c_double()
+    i32 = C.POINTER(C.c_int32)
+    rc = lib().pmg_adapt_multistage(ctx.h, mesh.h, orders.ctypes.data_as(i32), C.byref(ph), C.byref(p),
+                                    C.byref(prm), _ptr(Q), cap, out.ctypes.data_as(i32), C.byref(nn), reps,
+                                    C.byref(nrep), C.byref(cyc), C.byref(res), _stream())
+    if rc != 0 and not (rc == 5 and not raise_not_converged):
+        _check(rc)
+    n = int(nn.value)
+    reports = [{f: getattr(reps[i], f) for f, _ in StageReport._fields_ if f != "pad"} for i in range(nrep.value)]
+    return out, Q[:5 * n].view(5, n), reports, int(cyc.value), float(res.value)
 
 
 def device_bytes() -> int:
