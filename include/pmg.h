@@ -72,7 +72,7 @@ typedef struct {
   int32_t viscosity_model; /* 0 Sutherland's law, 1 constant viscosity */
 } pmg_physics;
 
-/* FAS p-multigrid (Sec. 3.1, Algorithm "FAS: V-Cycle"; Secs. 3.1.1-3.1.2; Sec. 3.2.4). */
+/* FAS p-multigrid (Sec. 3.1, Algorithm "FAS: V-Cycle"; Secs. 3.1.1-3.1.2; Sec. 3.3.3). */
 typedef struct {
   int32_t n_levels;          /* number of isotropic levels; 0 = max order (Delta N = 1 down to order 1) */
   const int32_t* level_caps; /* host, n_levels entries finest first, e.g. {3, 1}; NULL = max, max-1, ..., 1.
@@ -120,8 +120,8 @@ void pmg_mesh_destroy(pmg_mesh mesh);
 
 /*
  * Solver: mesh + order tensor (host, K*3 int32, each 1..7) + physics + multigrid parameters.  Builds the
- * isotropic level hierarchy (high-order coarsening, Sec. 3.2.4) and, lazily, the three one-direction
- * hierarchies of the anisotropic cycle (Sec. 3.2.3).  Metric terms are computed on the GPU for every
+ * isotropic level hierarchy (high-order coarsening, Sec. 3.3.3) and, lazily, the three one-direction
+ * hierarchies of the anisotropic cycle (Sec. 3.3.1).  Metric terms are computed on the GPU for every
  * level's own orders (curl form, Sec. 2).  The mesh must outlive the solver.
  */
 pmg_status pmg_solver_create(pmg_ctx ctx, pmg_mesh mesh, const int32_t* orders, const pmg_physics* phys,
@@ -180,7 +180,7 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
                      double* res_inf_out, void* stream);
 
 /*
- * Anisotropic truncation-error estimate inside the multigrid cycle (Secs. 3.2.1-3.2.3, eqs. TruncError!
+ * Anisotropic truncation-error estimate inside the multigrid cycle (Secs. 3.2.1 and 3.3.1, eqs. TruncError!
  * and AnisTruncError): one V-cycle per direction d, coarsening only d ("3V" cycle), each starting from the
  * previous one's result; Q_dev is smoothed in place by the three cycles.  At the entry of each coarse level
  * with cap n, tau = S_phys - A^n(I Q~) (isolated = 0, reusing the coarse-source operator evaluation) or
@@ -206,7 +206,7 @@ pmg_status pmg_checkpoint(pmg_solver s, const char* path, const double* Q_dev, v
 pmg_status pmg_restore(pmg_solver s, const char* path, double* Q_dev, void* stream);
 
 /*
- * Pointwise truncation error of one anisotropic level (Sec. 3.2.3; the quantity the tau map reduces): runs
+ * Pointwise truncation error of one anisotropic level (Sec. 3.3.1; the quantity the tau map reduces): runs
  * the anisotropic V-cycle of direction dir on Q_dev (as pmg_tau_estimate does for that direction, so Q_dev
  * is updated by that one cycle) and writes tau = S_phys - A(Q~0) (isolated = 0) or S_phys - A^(Q~0)
  * (isolated = 1) of the level whose order in dir is capped at 'order' (1 <= order < max order in dir) into

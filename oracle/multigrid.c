@@ -6,10 +6,10 @@
  * line of the printed algorithm writes the opposite sign, which would undo the coarse correction), fine
  * correction Q <- Q + I eps; recursive V-cycle with pre- and post-smoothing (Algorithm "FAS: V-Cycle");
  * Williamson's low-storage RK3 as smoother; L2 projection as restriction of both solution and residual,
- * exact interpolation as prolongation; Delta N = 1 with high-order coarsening (Sec. 3.2.4): the level with
+ * exact interpolation as prolongation; Delta N = 1 with high-order coarsening (Sec. 3.3.3): the level with
  * cap l keeps every order <= l and lowers the others to l, in all directions (isotropic cycle) or in one
  * direction (anisotropic cycle).  Residual-based smoothing tuning and FMG start (Secs. 3.1.1-3.1.2).
- * Truncation error estimate inside the cycle (Secs. 3.2.1-3.2.3): at the entry of every coarse level,
+ * Truncation error estimate inside the cycle (Secs. 3.2.1 and 3.3.1): at the entry of every coarse level,
  *   tau = S_phys - A^N(I Q~)   (non-isolated, reusing the A^N(I Q~) of the coarse source), or
  *   tau^ = S_phys - A^^N(I Q~) (isolated, one extra isolated operator evaluation),
  * with the physical source restricted level by level; one value per element, direction and order: the

@@ -1030,7 +1030,7 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// Hierarchies and the FAS V-cycle (Sec. 3.1, Algorithm "FAS: V-Cycle"; Sec. 3.2.3 anisotropic cycle)
+// Hierarchies and the FAS V-cycle (Sec. 3.1, Algorithm "FAS: V-Cycle"; Sec. 3.3.1 anisotropic cycle)
 // ------------------------------------------------------------------------------------------------
 // Levels below the top run in 'coarse_prec' (FP32 in the mixed-precision cycle); the top level is FP64.
 static void build_hier(pmg_solver_s* s, Hier& H, int dir, const std::vector<int>& caps_finest_first,

@@ -363,7 +363,7 @@ def test_isolated_equals_dg_for_continuous_state(oracle_mod, family):
 
 
 # ------------------------------------------------------------------------------------------------------
-# Sec. 3.1-3.2.3: FAS fixed point and the level-by-level estimator
+# Secs. 3.1, 3.2.1 and 3.3.1: FAS fixed point and the level-by-level estimator
 # ------------------------------------------------------------------------------------------------------
 def test_fas_fixed_point_and_one_shot_tau(oracle_mod):
     base = I.box_mesh((2, 2, 2), (-1, -1, -1), (1, 1, 1), M=(2, 2, 2), wobble=0.1)
