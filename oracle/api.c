@@ -220,3 +220,10 @@ void ora_operator_scale(or_problem* P, const int32_t* ord, int isolated, const d
   or_operator_ex(P, L, isolated, Q, A, scale);
   or_level_destroy(L);
 }
+
+/* Force on the no-slip walls: pressure part, viscous part, and the absolute sums of their terms (12 values). */
+void ora_wall_force(or_problem* P, const int32_t* ord, const double* Q, double* out) {
+  or_level* L = or_level_create(P, ord);
+  or_wall_force(P, L, Q, out);
+  or_level_destroy(L);
+}

@@ -78,6 +78,7 @@ void or_level_destroy(or_level* L);
 
 /* residual.c */
 void or_gradient(const or_problem* P, const or_level* L, int isolated, const double* Q, double* gW);
+void or_wall_force(const or_problem* P, const or_level* L, const double* Q, double out[12]);
 void or_operator(const or_problem* P, const or_level* L, int isolated, const double* Q, double* A);
 double or_timestep(const or_problem* P, const or_level* L, const double* Q);
 

@@ -77,6 +77,7 @@ def lib():
         L.ora_rk3_linear.restype = C.c_double
         L.ora_rk3_linear.argtypes = [C.c_double, C.c_double, C.c_double]
         L.ora_gradient.argtypes = [P, I32, C.c_int, D, D]
+        L.ora_wall_force.argtypes = [P, I32, D, D]
         L.ora_operator_scale.argtypes = [P, I32, C.c_int, D, D, D]
         L.ora_solve.restype = C.c_int
         L.ora_solve.argtypes = [P, I32, C.c_int, I32, C.POINTER(MGParams), D, D, C.c_double, C.c_int, D, D]
@@ -191,6 +192,13 @@ class Oracle:
         g = np.zeros((12, Q.shape[1]))
         lib().ora_gradient(self.h, _i32(self._ord(orders)), int(isolated), _d(Q), _d(g))
         return g.reshape(4, 3, -1)
+
+    def wall_force(self, orders, Q):
+        """(force on the no-slip walls: pressure part (3), viscous part (3); the sums of the absolute values of
+        the terms of each component (6), their round-off scale)."""
+        out = np.zeros(12)
+        lib().ora_wall_force(self.h, _i32(self._ord(orders)), _d(_f64(Q)), _d(out))
+        return out[:6], out[6:]
 
     def operator(self, orders, Q, isolated=False):
         Q = _f64(Q)

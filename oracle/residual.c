@@ -80,6 +80,11 @@ static void ghost(const or_phys* ph, int bc, const double q[5], const double n[3
     qg[0] = q[0];
     for (int c = 0; c < 3; c++) qg[1 + c] = q[1 + c] - 2.0 * mn * n[c];
     qg[4] = q[4];
+  } else if (bc == 4) { /* subsonic outflow: interior density and velocity, the far-field pressure */
+    double pinf = 1.0 / (ph->gamma * ph->mach * ph->mach);
+    double ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+    for (int c = 0; c < 4; c++) qg[c] = q[c];
+    qg[4] = pinf / (ph->gamma - 1.0) + ke;
   } else { /* far field */
     or_freestream(ph, qg);
   }
@@ -536,4 +541,57 @@ double or_timestep(const or_problem* P, const or_level* L, const double* Q) {
     }
   }
   return dt;
+}
+
+/*
+ * Force of the fluid on the no-slip walls (the drag and lift coefficients of Secs. 4.1 and 4.2 are its
+ * components over the dynamic pressure and a reference area): the surface integral over every wall face of
+ * p n - tau . n, with n the element's outward unit normal (into the wall), p and the viscous stress
+ * tau = (mu / Re)(grad v + grad v^T - 2/3 div v I) from the element's own traces of the state and of its BR1
+ * gradient, and the Gauss quadrature of the face nodes with the surface Jacobian.
+ * out[0..2]: pressure part, out[3..5]: viscous part, out[6..11]: the sums of the absolute values of the terms
+ * of each (their round-off scale).
+ */
+void or_wall_force(const or_problem* P, const or_level* L, const double* Q, double out[12]) {
+  const or_phys* ph = &P->ph;
+  const int64_t nn = L->nn, nf = L->nf;
+  double* qf = malloc(sizeof(double) * 5 * nf);
+  double* gW = malloc(sizeof(double) * 12 * nn);
+  double* gf = malloc(sizeof(double) * 12 * nf);
+  or_gradient(P, L, 0, Q, gW);
+  face_traces(P, L, Q, 5, qf);
+  face_traces(P, L, gW, 12, gf);
+  for (int i = 0; i < 12; i++) out[i] = 0.0;
+  for (int64_t e = 0; e < L->K; e++)
+    for (int f = 0; f < 6; f++) {
+      if (P->nbr[6 * e + f] >= 0 || P->bc[6 * e + f] != 1) continue;
+      int n[3], d, t1, t2;
+      elem_n(L, e, n);
+      face_axes(f, &d, &t1, &t2);
+      const or_basis1d* bs = &P->basis[n[t1] - 1];
+      const or_basis1d* bt = &P->basis[n[t2] - 1];
+      for (int b = 0; b < n[t2]; b++)
+        for (int a = 0; a < n[t1]; a++) {
+          int64_t fi = L->fo[6 * e + f] + a + (int64_t)n[t1] * b;
+          double q[5], g[4][3], N[3], nh[3], Fv[3][5], rho, v[3], p, T;
+          qvec(qf, nf, fi, q);
+          gvec(gf, nf, fi, g);
+          for (int c = 0; c < 3; c++) N[c] = L->Nout[c * nf + fi];
+          double Js = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+          for (int c = 0; c < 3; c++) nh[c] = N[c] / Js;
+          or_prim(ph, q, &rho, v, &p, &T);
+          or_flux_visc(ph, q, g, Fv);
+          double w = bs->w[a] * bt->w[b] * Js;
+          for (int i = 0; i < 3; i++) {
+            double tn = Fv[0][1 + i] * nh[0] + Fv[1][1 + i] * nh[1] + Fv[2][1 + i] * nh[2];
+            out[i] += w * p * nh[i];
+            out[3 + i] -= w * tn;
+            out[6 + i] += fabs(w * p * nh[i]);
+            out[9 + i] += fabs(w * tn);
+          }
+        }
+    }
+  free(qf);
+  free(gW);
+  free(gf);
 }

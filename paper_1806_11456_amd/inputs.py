@@ -29,7 +29,7 @@ from typing import Callable, Optional, Sequence
 
 import numpy as np
 
-BC_NONE, BC_WALL, BC_FARFIELD, BC_FREESLIP = 0, 1, 2, 3
+BC_NONE, BC_WALL, BC_FARFIELD, BC_FREESLIP, BC_OUTFLOW = 0, 1, 2, 3, 4
 FAMILY_LG, FAMILY_LGL = 0, 1
 
 # face f -> (normal axis, side) with side 0 at -1 and 1 at +1
@@ -473,6 +473,27 @@ def plate_mesh(nx: int = 64, ny: int = 32, ratio: float = 1.1) -> Mesh:
                     periodic=(False, False, True), ratio=(1.0, ratio, 1.0),
                     bc_lo=(BC_FARFIELD, BC_WALL, BC_NONE), bc_hi=(BC_FARFIELD, BC_FARFIELD, BC_NONE),
                     name=f"plate{nx}x{ny}")
+
+
+def plate_mesh_inflow_outflow(nx: int = 64, ny: int = 32, ratio: float = 1.1, x_lead: float = 0.25) -> Mesh:
+    """The plate mesh with the boundary layout of the paper's flat-plate case: uniform inflow (the far-field
+    state) at x = 0, free slip on y = 0 ahead of the plate (x < x_lead), the no-slip adiabatic plate behind
+    it, subsonic pressure outflow on the top and right sides."""
+    m = plate_mesh(nx, ny, ratio)
+    bc = m.bc.copy()
+    for e in range(m.K):
+        g = m.gnodes[e]
+        xc = 0.5 * (g[..., 0].min() + g[..., 0].max())
+        for f in range(6):
+            if m.nbr_elem[e, f] >= 0:
+                continue
+            if f == 2:  # y = 0
+                bc[e, f] = BC_FREESLIP if xc < x_lead else BC_WALL
+            elif f in (1, 3):  # x = 1, y = 0.5
+                bc[e, f] = BC_OUTFLOW
+    out = dataclasses.replace(m, bc=bc, name=f"plate{nx}x{ny}_io")
+    out.validate()
+    return out
 
 
 def config_plate(nx: int = 64, ny: int = 32, N=(6, 6, 1), seed: int = 2, amp: float = 1e-3) -> Workload:
