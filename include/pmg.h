@@ -21,8 +21,11 @@
  *   tangential reference coordinates in increasing axis order.  Orientation code o (0..7) of face f of
  *   element e towards its neighbour face f' maps (s, t) on e's face to (s', t') on the neighbour's face:
  *   (u, v) = (t, s) if (o & 4) else (s, t); s' = -u if (o & 1) else u; t' = -v if (o & 2) else v.
- * - Boundary tags: 0 interior or periodic (has a neighbour), 1 no-slip adiabatic wall, 2 far field,
- *   3 free-slip wall.  Far field is rho = 1, v = (1, 0, 0), p = 1 / (gamma M^2).
+ * - Boundary tags: 0 interior or periodic (has a neighbour), 1 no-slip adiabatic wall, 2 far field (also
+ *   the uniform inflow), 3 free-slip wall, 4 subsonic outflow with only the far-field pressure imposed (the
+ *   flat-plate case of Sec. 4.1).  Far field is rho = 1, v = (1, 0, 0), p = 1 / (gamma M^2); the outflow
+ *   ghost state keeps the interior density and velocity with that pressure.  The viscous flux on far field
+ *   and outflow faces is the interior one.
  * - Pointers named *_dev are device pointers on the solver's GPU; the caller owns them (for example the
  *   data_ptr() of torch tensors) and keeps them alive until the stream has consumed them.  Host arrays
  *   are copied during the call and may be freed afterwards.  The library owns its handles and every
@@ -415,6 +418,18 @@ pmg_status pmg_adapt_multistage(pmg_ctx ctx, pmg_mesh mesh, const int32_t* order
                                 int64_t capacity_nodes, int32_t* out_orders, int64_t* out_nodes,
                                 pmg_stage_report* reports, int32_t* n_reports, int32_t* final_cycles,
                                 double* final_res, void* stream);
+
+/*
+ * Force of the fluid on the no-slip walls (tag 1); its components over the dynamic pressure and a reference
+ * area are the drag and lift coefficients of Secs. 4.1 and 4.2 (with rho_inf = |v_inf| = 1: C = 2 F / A_ref,
+ * drag along v_inf = (1, 0, 0)).  F = the Gauss quadrature over every wall face of (p n - tau . n) dS, n the
+ * element's outward unit normal (into the wall), p from the element's trace of Q and tau . n the viscous
+ * traction of its BR1 gradient trace, tau = (mu / Re)(grad v + grad v^T - 2/3 div v I): the traces the
+ * residual's wall flux uses.  Q_dev [5][nn] (device, FP64) on the solver's finest level; force_host[6] (host):
+ * pressure part x, y, z, then viscous part x, y, z (zeros without wall faces).  Single-problem solvers only
+ * (PMG_ERR_INVALID_ARG otherwise); returns once the stream has completed.
+ */
+pmg_status pmg_wall_force(pmg_solver s, const double* Q_dev, double* force_host, void* stream);
 
 #ifdef __cplusplus
 }

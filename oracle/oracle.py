@@ -194,8 +194,8 @@ class Oracle:
         return g.reshape(4, 3, -1)
 
     def wall_force(self, orders, Q):
-        """(force on the no-slip walls: pressure part (3), viscous part (3); the sums of the absolute values of
-        the terms of each component (6), their round-off scale)."""
+        """(force on the no-slip walls: pressure part (3), viscous part (3); the round-off scale of each
+        component (6): the sum over the wall nodes of the length of the node's vector term)."""
         out = np.zeros(12)
         lib().ora_wall_force(self.h, _i32(self._ord(orders)), _d(_f64(Q)), _d(out))
         return out[:6], out[6:]

@@ -549,8 +549,9 @@ double or_timestep(const or_problem* P, const or_level* L, const double* Q) {
  * p n - tau . n, with n the element's outward unit normal (into the wall), p and the viscous stress
  * tau = (mu / Re)(grad v + grad v^T - 2/3 div v I) from the element's own traces of the state and of its BR1
  * gradient, and the Gauss quadrature of the face nodes with the surface Jacobian.
- * out[0..2]: pressure part, out[3..5]: viscous part, out[6..11]: the sums of the absolute values of the terms
- * of each (their round-off scale).
+ * out[0..2]: pressure part, out[3..5]: viscous part, out[6..11]: the round-off scale of each component, the
+ * sum over the nodes of the magnitude of the node's vector term (w J_s |p| for the pressure part, w J_s |tau . n|
+ * for the viscous part): rounding moves a node's term relative to its length, whatever its direction.
  */
 void or_wall_force(const or_problem* P, const or_level* L, const double* Q, double out[12]) {
   const or_phys* ph = &P->ph;
@@ -581,13 +582,16 @@ void or_wall_force(const or_problem* P, const or_level* L, const double* Q, doub
           for (int c = 0; c < 3; c++) nh[c] = N[c] / Js;
           or_prim(ph, q, &rho, v, &p, &T);
           or_flux_visc(ph, q, g, Fv);
-          double w = bs->w[a] * bt->w[b] * Js;
+          double w = bs->w[a] * bt->w[b] * Js, tn[3];
           for (int i = 0; i < 3; i++) {
-            double tn = Fv[0][1 + i] * nh[0] + Fv[1][1 + i] * nh[1] + Fv[2][1 + i] * nh[2];
+            tn[i] = Fv[0][1 + i] * nh[0] + Fv[1][1 + i] * nh[1] + Fv[2][1 + i] * nh[2];
             out[i] += w * p * nh[i];
-            out[3 + i] -= w * tn;
-            out[6 + i] += fabs(w * p * nh[i]);
-            out[9 + i] += fabs(w * tn);
+            out[3 + i] -= w * tn[i];
+          }
+          double tl = sqrt(tn[0] * tn[0] + tn[1] * tn[1] + tn[2] * tn[2]);
+          for (int i = 0; i < 3; i++) {
+            out[6 + i] += fabs(w * p);
+            out[9 + i] += w * tl;
           }
         }
     }

@@ -208,7 +208,8 @@ __device__ __forceinline__ void freestream(const Phys& P, T q[5]) {
   q[0] = T(1); q[1] = T(1); q[2] = T(0); q[3] = T(0); q[4] = T(P.rhoE_inf);
 }
 
-// ghost state of a boundary node (unit outward normal n)
+// ghost state of a boundary node (unit outward normal n): 1 no-slip adiabatic wall, 2 far field (uniform
+// inflow), 3 free slip, 4 subsonic outflow with the far-field pressure
 template <class T>
 __device__ __forceinline__ void ghost_state(const Phys& P, int bc, const T q[5], const T n[3], T g[5]) {
   if (bc == 1) {
@@ -217,6 +218,10 @@ __device__ __forceinline__ void ghost_state(const Phys& P, int bc, const T q[5],
     T mn = q[1] * n[0] + q[2] * n[1] + q[3] * n[2];
     g[0] = q[0]; g[1] = q[1] - T(2) * mn * n[0]; g[2] = q[2] - T(2) * mn * n[1]; g[3] = q[3] - T(2) * mn * n[2];
     g[4] = q[4];
+  } else if (bc == 4) {
+    // subsonic outflow: the interior density and velocity with the far-field pressure
+    g[0] = q[0]; g[1] = q[1]; g[2] = q[2]; g[3] = q[3];
+    g[4] = T(P.pinf) / T(P.gm1) + T(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
   } else {
     freestream(P, g);
   }

@@ -159,6 +159,12 @@ struct Level {
   int *d_wlink = nullptr, *d_mlink = nullptr, *d_f1list = nullptr;
   int4* d_fcrec = nullptr;  // conforming / boundary face tiles: {first mortar node, end, problem, 0}
   int2* d_cmap = nullptr;
+  // quadrature of the no-slip wall faces: mortar node and Gauss weight w_s w_t of every wall node (host),
+  // uploaded on the first wall-force evaluation
+  std::vector<int> wall_mn;
+  std::vector<double> wall_w;
+  int* d_wall_mn = nullptr;
+  double* d_wall_w = nullptr;
   int* d_ptile = nullptr;  // [nprob + 1]: the element tiles of each problem (contiguous)
   int4* d_tiles;
   FaceRec* d_faces;
@@ -545,6 +551,17 @@ static std::shared_ptr<Level> build_level(pmg_solver_s* s, const std::vector<int
     }
   }
   REQUIRE(L->nfl_conf + L->nfl_bnd + L->nfl_nc == nf, "face nodes not covered by the interfaces");
+  for (const FaceRec& F : faces)
+    if (F.eS < 0 && F.bc == 1) {
+      double xs[PMG_MAXN], ws[PMG_MAXN], xt[PMG_MAXN], wt[PMG_MAXN];
+      hb::nodes(F.nMs, L->fam, xs, ws);
+      hb::nodes(F.nMt, L->fam, xt, wt);
+      for (int b = 0; b < F.nMt; b++)
+        for (int a = 0; a < F.nMs; a++) {
+          L->wall_mn.push_back(F.mbase + a + F.nMs * b);
+          L->wall_w.push_back(ws[a] * wt[b]);
+        }
+    }
 
   std::vector<int> node_elem(nn);
   for (int e = 0; e < K; e++)
@@ -1597,7 +1614,7 @@ pmg_status pmg_mesh_create(pmg_ctx ctx, int64_t K, const int32_t M[3], const dou
       for (int f = 0; f < 6; f++) {
         int64_t g = nbr_elem[6 * e + f];
         if (g < 0) {
-          REQUIRE(bc[6 * e + f] >= 1 && bc[6 * e + f] <= 3, "boundary face without a boundary tag");
+          REQUIRE(bc[6 * e + f] >= 1 && bc[6 * e + f] <= 4, "boundary face without a boundary tag (1..4)");
           continue;
         }
         REQUIRE(g < K, "neighbour index out of range");
@@ -2440,3 +2457,4 @@ pmg_status pmg_profile_read(pmg_solver s, int kind, double* total_ms, int64_t* l
 }  // extern "C"
 
 #include "adapt.inc"
+#include "functionals.inc"

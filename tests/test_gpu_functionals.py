@@ -1,0 +1,101 @@
+"""Subsonic outflow and the wall force on the GPU against the oracle (and the Couette closed form).
+
+* Residual (DG and isolated) on the plate with the paper's inflow / free-slip / wall / outflow layout: every
+  entry at the 1e-12 bar of the operator's round-off scale, small and full size.
+* Wall force (pressure and viscous parts): plate, plate with the paper's layout, the rotated O-grid with random
+  orders (p-nonconforming faces, every orientation), the full-size plate; each component within 1e-12 of the
+  sum of the absolute values of its terms.  The Couette channel against its closed form.
+"""
+import numpy as np
+import pytest
+
+from paper_1806_11456_amd import inputs as I
+from tests.gpu_util import check, np_, small_cases
+
+pytestmark = pytest.mark.gpu
+
+CASES = small_cases()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1806_11456_amd import pmg
+    assert torch.cuda.is_available()
+    return pmg.Context(0)
+
+
+def io_plate(nx=8, ny=4, seed=31):
+    wl = I.config_plate(nx, ny)
+    mesh = I.plate_mesh_inflow_outflow(nx, ny)
+    Q = I.perturbed_freestream(wl.Q.shape[1], wl.phys.mach, 0.02, seed)
+    return I.Workload(mesh.name, mesh, wl.orders, wl.phys, Q)
+
+
+def pair(ctx, wl):
+    from oracle import oracle as O
+    from paper_1806_11456_amd import pmg
+    s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys, pmg.MG(level_caps=[int(wl.orders.max())]))
+    return s, O.Oracle(wl.mesh, wl.phys)
+
+
+@pytest.mark.parametrize("size", ["small", "full"])
+def test_outflow_residual(ctx, size):
+    wl = io_plate() if size == "small" else io_plate(64, 32)
+    s, o = pair(ctx, wl)
+    rng = np.random.default_rng(5)
+    S = 0.1 * rng.uniform(-1, 1, size=wl.Q.shape)
+    for iso in (False, True):
+        Rg = np_(s.residual(s.tensor(wl.Q), s.tensor(S), isolated=iso))
+        Ro = o.residual(wl.orders, wl.Q, S, isolated=iso)
+        _, sc = o.operator_scale(wl.orders, wl.Q, isolated=iso)
+        check(Rg, Ro, sc, 1e-12, f"io plate {size} residual iso={iso}")
+
+
+def _force_case(name):
+    if name == "plate8x4":
+        wl = CASES["plate8x4"]
+        return wl, I.perturbed_freestream(wl.Q.shape[1], wl.phys.mach, 0.02, 41)
+    if name == "io_plate":
+        wl = io_plate()
+        return wl, wl.Q
+    if name == "ogrid2x2":
+        return CASES["ogrid2x2"], CASES["ogrid2x2"].Q
+    wl = I.config_plate()
+    return wl, wl.Q
+
+
+@pytest.mark.parametrize("name", ["plate8x4", "io_plate", "ogrid2x2", "plate_full"])
+def test_wall_force_matches_oracle(ctx, name):
+    wl, Q = _force_case(name)
+    s, o = pair(ctx, wl)
+    Fg = s.wall_force(s.tensor(Q))
+    Fo, sc = o.wall_force(wl.orders, Q)
+    assert np.all(sc > 0)
+    err = np.abs(Fg - Fo)
+    assert np.all(err <= 1e-12 * sc), (name, Fg, Fo, err / sc)
+
+
+def test_wall_force_couette_closed_form(ctx):
+    """u = 2y on the stretched curved channel (wall at y = 0, far field at y = 0.5): F = (2A/Re, -p_inf A, 0)."""
+    from paper_1806_11456_amd import pmg
+    from tests.test_oracle_functionals import channel, couette_state
+    phys = I.Physics(mach=0.2, reynolds=500.0, family=I.FAMILY_LG)
+    mesh = channel()
+    orders = I.uniform_orders(mesh.K, (4, 4, 4))
+    Q = couette_state(mesh, orders, phys)
+    s = pmg.Solver(ctx, pmg.Mesh(ctx, mesh), orders, phys, pmg.MG(level_caps=[4]))
+    F = s.wall_force(s.tensor(Q))
+    pinf = 1.0 / (phys.gamma * phys.mach ** 2)
+    A = 0.05
+    want = np.array([0.0, -pinf * A, 0.0, 2.0 * A / phys.reynolds, 0.0, 0.0])
+    assert np.all(np.abs(F - want) <= 1e-12 * np.array([pinf * A] * 3 + [2.0 * A / phys.reynolds] * 3)), F
+    cd, cl = pmg.force_coefficients(F, A)
+    assert abs(cd - 4.0 / phys.reynolds) <= 1e-12 and abs(cl + 2.0 * pinf) <= 1e-12 * pinf
+
+
+def test_wall_force_without_walls_and_batches(ctx):
+    from paper_1806_11456_amd import pmg
+    wl = CASES["box_lgl"]  # periodic: no wall faces
+    s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys)
+    assert (s.wall_force(s.tensor(wl.Q)) == 0).all()
