@@ -203,6 +203,71 @@ def solve_bench(args) -> dict:
     return out
 
 
+def compare_bench(args) -> dict:
+    """Pure explicit RK3, the isotropic FAS V-cycle and the anisotropic FAS (the 3V cycle: one V-cycle per
+    direction, each coarsening only that direction) as solvers of the flat plate from the far-field state,
+    each for a bounded wall time, the residual norm read after every chunk.  The speed-up of a method over
+    RK3 is the ratio of the times the two first reach the lowest residual that every method reaches (the
+    paper compares the times to a converged residual, which pure RK3 does not reach in a bounded run)."""
+    import torch
+
+    from paper_1806_11456_amd import inputs as I
+    from paper_1806_11456_amd import pmg
+
+    wl = I.config_plate()
+    ctx = pmg.Context(0)
+    mg = pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4)
+    mesh = pmg.Mesh(ctx, wl.mesh)
+
+    def run(name, chunk, advance):
+        s = pmg.Solver(ctx, mesh, wl.orders, wl.phys, mg)
+        s.set_graph(True)
+        Q = s.freestream()
+        r0 = s.residual(Q, None, norm=True)[1]
+        hist = [(0.0, 0, r0)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < args.compare_s:
+            advance(s, Q, chunk)
+            n += chunk
+            r = s.residual(Q, None, norm=True)[1]
+            hist.append((time.perf_counter() - t0, n, r))
+            if r != r:
+                break
+            if len(hist) % 20 == 0:
+                print(f"compare {name}: {n} after {hist[-1][0]:.1f} s, residual {r:.3e}", file=sys.stderr, flush=True)
+        return hist
+
+    hist = {
+        "rk3": run("rk3", args.compare_rk_chunk, lambda s, Q, c: s.smooth(Q, None, sweeps=c)),
+        "fas_isotropic": run("fas_isotropic", args.compare_fas_chunk, lambda s, Q, c: s.vcycle(Q, None, n_cycles=c)),
+        "fas_anisotropic": run("fas_anisotropic", args.compare_aniso_chunk,
+                               lambda s, Q, c: [s.tau_estimate(Q, None, isolated=False) for _ in range(c)]),
+    }
+    best = {m: min(r for _, _, r in h) for m, h in hist.items()}
+    level = max(best.values())
+
+    def first(h):
+        return next((t, n) for t, n, r in h if r <= level)
+
+    reach = {m: first(h) for m, h in hist.items()}
+    t_rk = reach["rk3"][0]
+    speed = {m: (t_rk / t if t > 0 and t_rk > 0 else None) for m, (t, _) in reach.items()}
+    return {"metric": "speed-up over RK3 at equal residual", "value": speed["fas_isotropic"], "unit": "x",
+            "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "flat-plate boundary layer: 64x32x1 stretched hexes (ratio 1.1), quadratic "
+                                   "mapping, N=(6,6,1) Gauss, Mach 0.2, Re_L 1e5, wall + far field; far-field start",
+                       "seconds_per_method": args.compare_s, "fas": "levels 6..1, beta 2/2/4, graph replay",
+                       "units": {"rk3": "sweeps", "fas_isotropic": "V-cycles",
+                                 "fas_anisotropic": "3V cycles (x and y; z has order 1)"}},
+            "level": level, "speedup": speed,
+            "time_to_level_s": {m: t for m, (t, _) in reach.items()},
+            "work_to_level": {m: n for m, (_, n) in reach.items()},
+            "best_residual": best,
+            "history": {m: [(round(t, 3), n, r) for t, n, r in h[:: max(1, len(h) // 40)]] for m, h in hist.items()}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +292,11 @@ def main() -> int:
     ap.add_argument("--solve-max-cycles", type=int, default=400000)
     ap.add_argument("--solve-max-s", type=float, default=1000.0)
     ap.add_argument("--solve-precision", type=int, default=0)
+    ap.add_argument("--compare", action="store_true", help="RK3 against FAS: speed-up at equal residual")
+    ap.add_argument("--compare-s", type=float, default=40.0)
+    ap.add_argument("--compare-rk-chunk", type=int, default=1000)
+    ap.add_argument("--compare-fas-chunk", type=int, default=20)
+    ap.add_argument("--compare-aniso-chunk", type=int, default=10)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -240,6 +310,9 @@ def main() -> int:
         return 0
     if args.solve:
         print(json.dumps(solve_bench(args)), flush=True)
+        return 0
+    if args.compare:
+        print(json.dumps(compare_bench(args)), flush=True)
         return 0
 
     import numpy as np
