@@ -268,6 +268,56 @@ def compare_bench(args) -> dict:
             "history": {m: [(round(t, 3), n, r) for t, n, r in h[:: max(1, len(h) // 40)]] for m, h in hist.items()}}
 
 
+def sphere_bench(args) -> dict:
+    """Soft physics check (not parity): steady flow past the unit sphere at Re_D = 200, Mach 0.2 (Re = 100 on
+    the radius), the six-panel O-grid (8 x 8 x 13 hexes per panel, outer radius 20, quadratic mapping) at
+    uniform order N, FAS V-cycles on levels N..2 from the far-field state; the drag coefficient
+    C_d = 2 F_x / (pi r^2) after every chunk of cycles, for comparison with the paper's 0.7771."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1806_11456_amd import inputs as I
+    from paper_1806_11456_amd import pmg
+
+    N = args.sphere_order
+    mesh = I.ogrid_mesh(8, 13, r_out=20.0, ratio=1.25)
+    orders = I.uniform_orders(mesh.K, (N, N, N))
+    phys = I.Physics(mach=0.2, reynolds=100.0, family=I.FAMILY_LG, cfl_adv=args.sphere_cfl,
+                     cfl_visc=args.sphere_cfl)
+    ctx = pmg.Context(0)
+    s = pmg.Solver(ctx, pmg.Mesh(ctx, mesh), orders, phys,
+                   pmg.MG(level_caps=list(range(N, 1, -1)), beta_pre=2, beta_post=2, beta_coarse=4))
+    s.set_graph(True)
+    Q = s.freestream()
+    area = math.pi
+    hist = []
+    t0 = time.perf_counter()
+    cycles = 0
+    r = s.residual(Q, None, norm=True)[1]
+    while time.perf_counter() - t0 < args.sphere_s and r > args.sphere_tol:
+        r = s.vcycle(Q, None, n_cycles=args.sphere_chunk, norm=True)
+        cycles += args.sphere_chunk
+        if r != r:
+            break
+        F = s.wall_force(Q)
+        cd, cl = pmg.force_coefficients(F, area)
+        hist.append((cycles, round(time.perf_counter() - t0, 2), r, cd, cl, float(2 * F[0] / area),
+                     float(2 * F[3] / area)))
+        print(f"sphere: {cycles} cycles, {hist[-1][1]:.1f} s, residual {r:.3e}, C_d {cd:.5f} "
+              f"(pressure {hist[-1][5]:.5f}, viscous {hist[-1][6]:.5f}), C_l {cl:.2e}", file=sys.stderr, flush=True)
+    last = hist[-1] if hist else None
+    return {"metric": "sphere drag coefficient (soft physics check)", "value": last[3] if last else None,
+            "unit": "C_d", "higher_is_better": None, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "sphere, Re_D 200, Mach 0.2: six-panel O-grid 8x8x13 per panel (4992 hexes), "
+                                   "outer radius 20, radial ratio 1.25, quadratic mapping, far-field start",
+                       "order": N, "dof": s.n_nodes, "levels": list(range(N, 1, -1)), "beta": [2, 2, 4],
+                       "cfl": args.sphere_cfl},
+            "paper_cd": 0.7771, "cycles": cycles, "residual": r,
+            "history": hist[:: max(1, len(hist) // 30)] + ([last] if last else [])}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +343,12 @@ def main() -> int:
     ap.add_argument("--solve-max-s", type=float, default=1000.0)
     ap.add_argument("--solve-precision", type=int, default=0)
     ap.add_argument("--compare", action="store_true", help="RK3 against FAS: speed-up at equal residual")
+    ap.add_argument("--sphere", action="store_true", help="sphere drag at Re_D 200 (soft physics check)")
+    ap.add_argument("--sphere-order", type=int, default=4)
+    ap.add_argument("--sphere-cfl", type=float, default=0.3)
+    ap.add_argument("--sphere-s", type=float, default=240.0)
+    ap.add_argument("--sphere-chunk", type=int, default=200)
+    ap.add_argument("--sphere-tol", type=float, default=1e-7)
     ap.add_argument("--compare-s", type=float, default=40.0)
     ap.add_argument("--compare-rk-chunk", type=int, default=1000)
     ap.add_argument("--compare-fas-chunk", type=int, default=20)
@@ -313,6 +369,9 @@ def main() -> int:
         return 0
     if args.compare:
         print(json.dumps(compare_bench(args)), flush=True)
+        return 0
+    if args.sphere:
+        print(json.dumps(sphere_bench(args)), flush=True)
         return 0
 
     import numpy as np
