@@ -318,6 +318,94 @@ def sphere_bench(args) -> dict:
             "history": hist[:: max(1, len(hist) // 30)] + ([last] if last else [])}
 
 
+def sphere_adapt_bench(args) -> dict:
+    """The structure of the paper's single-stage adaptation of the sphere (Sec. 4.2): the sphere of
+    sphere_bench converged at uniform P = 4, its isolated truncation-error map estimated by the anisotropic
+    3V cycle (on a copy of the state), new orders for a few tau_max with the 3-D rules (the floor(2N/3)
+    order-jump rule, conforming orders on the wall, n_max = 6) and n_min = 4: with the quadratic mapping
+    (M = 2) the curl-form metric keeps the free stream on p-nonconforming faces only for N >= 2M; the state
+    carried over and the adapted problem converged; C_d of each against a uniform order-6 reference solved the
+    same way (or given by --sphere-ref-cd from an earlier run)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1806_11456_amd import inputs as I
+    from paper_1806_11456_amd import pmg
+
+    mesh_h = I.ogrid_mesh(8, 13, r_out=20.0, ratio=1.25)
+    phys = I.Physics(mach=0.2, reynolds=100.0, family=I.FAMILY_LG, cfl_adv=args.sphere_cfl,
+                     cfl_visc=args.sphere_cfl)
+    ctx = pmg.Context(0)
+    mesh = pmg.Mesh(ctx, mesh_h)
+    area = math.pi
+
+    def solver(orders):
+        top = int(orders.max())
+        s = pmg.Solver(ctx, mesh, orders, phys,
+                       pmg.MG(level_caps=list(range(top, 1, -1)), beta_pre=2, beta_post=2, beta_coarse=4))
+        s.set_graph(True)
+        return s
+
+    def converge(s, Q, label):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cycles, r = 0, s.residual(Q, None, norm=True)[1]
+        while r > args.sphere_tol and time.perf_counter() - t0 < args.sphere_s and r == r:
+            r = s.vcycle(Q, None, n_cycles=args.sphere_chunk, norm=True)
+            cycles += args.sphere_chunk
+            if cycles % (10 * args.sphere_chunk) == 0:
+                print(f"sphere-adapt {label}: {cycles} cycles, {time.perf_counter() - t0:.1f} s, residual {r:.3e}",
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        cd = pmg.force_coefficients(s.wall_force(Q), area)[0]
+        out = {"label": label, "dof": s.n_nodes, "cycles": cycles, "residual": r,
+               "solve_s": round(time.perf_counter() - t0, 2), "cd": cd}
+        print(f"sphere-adapt {label}: {out}", file=sys.stderr, flush=True)
+        return out
+
+    K = mesh_h.K
+    runs = []
+    if args.sphere_ref_cd:
+        ref = {"label": "uniform N=6 (reference, earlier run)", "dof": 1712256, "cd": args.sphere_ref_cd}
+    else:
+        ref_orders = I.uniform_orders(K, (6, 6, 6))
+        sr = solver(ref_orders)
+        ref = converge(sr, sr.freestream(), "uniform N=6 (reference)")
+        del sr
+    P = I.uniform_orders(K, (4, 4, 4))
+    s4 = solver(P)
+    Q4 = s4.freestream()
+    runs.append(converge(s4, Q4, "uniform N=4"))
+    tau = s4.tau_estimate(Q4.clone(), None, isolated=True).cpu().numpy()
+    vals = tau[np.isfinite(tau) & (tau > 0)]
+    for q in args.sphere_quantiles:
+        tau_max = float(np.quantile(vals, q))
+        t0 = time.perf_counter()
+        N, req = pmg.adapt_orders(mesh_h, P, tau, tau_max, (6, 6, 6), args.sphere_nmin, 2, True,
+                                  with_required=True)
+        sa = solver(N)
+        Qa = pmg.remap_state(s4, Q4, sa)
+        torch.cuda.synchronize()
+        prep = time.perf_counter() - t0
+        run = converge(sa, Qa, f"adapted tau_max={tau_max:.3e}")
+        run.update({"tau_max": tau_max, "quantile": q, "max_required": req, "adapt_s": round(prep, 3),
+                    "orders_hist": np.bincount(N.ravel(), minlength=8)[1:].tolist()})
+        runs.append(run)
+        del sa, Qa
+    for r in runs + [ref]:
+        r["cd_error"] = abs(r["cd"] - ref["cd"]) / ref["cd"]
+    return {"metric": "sphere drag error vs DOF after tau-based adaptation", "value": None, "unit": "relative",
+            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "sphere, Re_D 200, Mach 0.2, six-panel O-grid 8x8x13 per panel (4992 hexes), "
+                                   "outer radius 20, quadratic mapping", "tol": args.sphere_tol,
+                       "adapt": f"isolated 3V map at P=4, n_min {args.sphere_nmin}, n_max 6, jump rule "
+                                "floor(2N/3), wall conforming",
+                       "levels": "max order .. 2, beta 2/2/4"},
+            "reference": ref, "runs": runs}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +437,10 @@ def main() -> int:
     ap.add_argument("--sphere-s", type=float, default=240.0)
     ap.add_argument("--sphere-chunk", type=int, default=200)
     ap.add_argument("--sphere-tol", type=float, default=1e-7)
+    ap.add_argument("--sphere-adapt", action="store_true", help="sphere drag error vs DOF after adaptation")
+    ap.add_argument("--sphere-quantiles", type=float, nargs="+", default=[0.3, 0.6, 0.9])
+    ap.add_argument("--sphere-nmin", type=int, default=4)
+    ap.add_argument("--sphere-ref-cd", type=float, default=0.0)
     ap.add_argument("--compare-s", type=float, default=40.0)
     ap.add_argument("--compare-rk-chunk", type=int, default=1000)
     ap.add_argument("--compare-fas-chunk", type=int, default=20)
@@ -372,6 +464,9 @@ def main() -> int:
         return 0
     if args.sphere:
         print(json.dumps(sphere_bench(args)), flush=True)
+        return 0
+    if args.sphere_adapt:
+        print(json.dumps(sphere_adapt_bench(args)), flush=True)
         return 0
 
     import numpy as np
