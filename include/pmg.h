@@ -367,8 +367,8 @@ pmg_status pmg_adapt_orders(int64_t K, const int64_t* nbr_elem, const int32_t* n
  * orders).  Per element and direction: exact interpolation where the order rises (the prolongation of
  * eq. FASCorrectSol), the L2 projection of the restriction (eq. FASCoarseSol, Sec. 3.1) where it falls, the
  * identity where it is unchanged;
- * tensor product over the three directions.  Both solvers hold one problem each, on the same mesh handle and
- * node family.  Q_from_dev [5][nn_from] and Q_to_dev [5][nn_to]: device, FP64, caller-owned, layouts of
+ * tensor product over the three directions.  Both solvers hold one problem each, on the same mesh (one handle,
+ * or two handles created from identical mesh data) and node family.  Q_from_dev [5][nn_from] and Q_to_dev [5][nn_to]: device, FP64, caller-owned, layouts of
  * pmg_state_layout.  Enqueued on 'stream'; returns once it has completed.
  */
 pmg_status pmg_remap_state(pmg_solver from, const double* Q_from_dev, pmg_solver to, double* Q_to_dev,

@@ -155,6 +155,24 @@ def test_remap_matches_oracle(ctx, name):
     check(got, want, None, 1e-13, f"{name} remap")
 
 
+def test_remap_mesh_checks(ctx):
+    """Two handles of identical mesh data count as one mesh (same result as one handle); a different mesh is
+    rejected."""
+    from paper_1806_11456_amd import pmg
+    wl = CASES["curved_lg"]
+    B = np.random.default_rng(3).integers(1, 8, size=(wl.mesh.K, 3)).astype(np.int32)
+    m1, m2 = pmg.Mesh(ctx, wl.mesh), pmg.Mesh(ctx, wl.mesh)
+    sa = pmg.Solver(ctx, m1, wl.orders, wl.phys, pmg.MG(level_caps=[7]))
+    sb1 = pmg.Solver(ctx, m1, B, wl.phys, pmg.MG(level_caps=[7]))
+    sb2 = pmg.Solver(ctx, m2, B, wl.phys, pmg.MG(level_caps=[7]))
+    Q = sa.tensor(wl.Q)
+    assert np.array_equal(np_(pmg.remap_state(sa, Q, sb1)), np_(pmg.remap_state(sa, Q, sb2)))
+    other = CASES["ogrid2x2"]
+    so = pmg.Solver(ctx, pmg.Mesh(ctx, other.mesh), other.orders, other.phys, pmg.MG(level_caps=[7]))
+    with pytest.raises(pmg.PmgError, match="same mesh"):
+        pmg.remap_state(sa, Q, so)
+
+
 def test_multistage_matches_oracle(ctx):
     """Small plate, stages (3, 5, 6) from free stream with FMG: the orders of every stage, the reports and the
     final state equal the oracle's driver.  Each solve runs its max_cycles (tolerances out of reach), so both

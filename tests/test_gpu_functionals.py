@@ -95,7 +95,13 @@ def test_wall_force_couette_closed_form(ctx):
 
 
 def test_wall_force_without_walls_and_batches(ctx):
+    """No wall faces: zeros.  A batch solver (several problems): rejected, the force is per problem."""
     from paper_1806_11456_amd import pmg
     wl = CASES["box_lgl"]  # periodic: no wall faces
     s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys)
     assert (s.wall_force(s.tensor(wl.Q)) == 0).all()
+    pl = CASES["plate8x4"]
+    b = pmg.Batch(ctx, [pmg.Mesh(ctx, pl.mesh), pmg.Mesh(ctx, pl.mesh)], [pl.orders, pl.orders],
+                  [pl.phys, pl.phys], pmg.MG())
+    with pytest.raises(pmg.PmgError, match="single-problem"):
+        b.wall_force(b.empty())
