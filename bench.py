@@ -406,6 +406,80 @@ def sphere_adapt_bench(args) -> dict:
             "reference": ref, "runs": runs}
 
 
+def sphere_multistage_bench(args) -> dict:
+    """The structure of the paper's multi-stage comparison on the sphere (Sec. 4.2, its Table 3), both runs
+    through the library's driver (pmg_adapt_multistage): single-stage, converging uniform P = 6 before the one
+    estimate and adaptation; multi-stage, stages (4, 6) from uniform 4 (orders capped at 6 after the first
+    estimate, a second estimate and adaptation at the stage-6 orders when some element asks for more).  Same
+    tau_max, n_max (6 by default), n_min = 4 (N >= 2M for the quadratic mapping), floor(2N/3) jump rule,
+    conforming wall orders, stage solves to tau_max / 10, FMG start, levels down to order 2, final solve to
+    the tolerance;
+    wall time of each driver call and C_d of its result."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1806_11456_amd import inputs as I
+    from paper_1806_11456_amd import pmg
+
+    mesh_h = I.ogrid_mesh(8, 13, r_out=20.0, ratio=1.25)
+    phys = I.Physics(mach=0.2, reynolds=100.0, family=I.FAMILY_LG, cfl_adv=args.sphere_cfl,
+                     cfl_visc=args.sphere_cfl)
+    ctx = pmg.Context(0)
+    mesh = pmg.Mesh(ctx, mesh_h)
+    mg = pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4, fmg=1, fmg_threshold=1.0)
+    K = mesh_h.K
+    out = {}
+    for label, first, stages in (("single-stage", 6, (6,)), ("multi-stage", 4, (4, 6))):
+        print(f"sphere-multistage {label}: start", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # the driver runs the stages and the carry-over (final_tol out of reach from above: no final cycles);
+        # the final solve continues here in chunks, with progress lines, on a solver like the driver's
+        N, Q, reps, _, _ = pmg.adapt_multistage(
+            ctx, mesh, I.uniform_orders(K, (first,) * 3), phys, mg, stages, args.sphere_tau_max,
+            (args.sphere_nmax,) * 3, 4, 2,
+            True, conv=0.1, final_tol=1e30, max_cycles=args.sphere_max_cycles, raise_not_converged=False,
+            n_coarse=2)
+        torch.cuda.synchronize()
+        t_stages = time.perf_counter() - t0
+        print(f"sphere-multistage {label}: stages done in {t_stages:.1f} s: {reps}", file=sys.stderr, flush=True)
+        top = int(N.max())
+        s = pmg.Solver(ctx, mesh, N, phys, pmg.MG(level_caps=list(range(top, 1, -1)), beta_pre=2, beta_post=2,
+                                                beta_coarse=4))
+        Q = Q.clone()
+        cyc, res = 0, s.residual(Q, None, norm=True)[1]
+        while res > args.sphere_tol and cyc < args.sphere_max_cycles and res == res:
+            res = s.vcycle(Q, None, n_cycles=args.sphere_chunk, norm=True)
+            cyc += args.sphere_chunk
+            if cyc % (10 * args.sphere_chunk) == 0 or cyc <= 5 * args.sphere_chunk:
+                print(f"sphere-multistage {label}: final solve {cyc} cycles, {time.perf_counter() - t0:.1f} s, "
+                      f"residual {res:.3e}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        cd = pmg.force_coefficients(s.wall_force(Q), math.pi)[0]
+        out[label] = {"wall_s": round(wall, 2), "stages_s": round(t_stages, 2), "cd": cd, "final_cycles": cyc,
+                      "final_residual": res,
+                      "dof": int(Q.shape[1]), "orders_hist": np.bincount(N.ravel(), minlength=8)[1:].tolist(),
+                      "stages": [{k: (int(v) if isinstance(v, (int, np.integer)) else float(v))
+                                  for k, v in r.items()} for r in reps]}
+        print(f"sphere-multistage {label}: {out[label]}", file=sys.stderr, flush=True)
+        del s, Q
+    ref = args.sphere_ref_cd or None
+    for v in out.values():
+        v["cd_error_vs_order6"] = abs(v["cd"] - ref) / ref if ref else None
+    return {"metric": "multi-stage vs single-stage adaptation, sphere", "unit": "s", "higher_is_better": False,
+            "value": (out["single-stage"]["wall_s"] / out["multi-stage"]["wall_s"]), "value_meaning":
+                "speed-up of the multi-stage run over the single-stage run (wall time of the driver calls)",
+            "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "sphere, Re_D 200, Mach 0.2, six-panel O-grid 8x8x13 per panel (4992 hexes)",
+                       "tau_max": args.sphere_tau_max, "tol": args.sphere_tol, "n_max": args.sphere_nmax, "n_min": 4,
+                       "jump_rule": "floor(2N/3)", "wall_conforming": True, "levels": "max .. 2",
+                       "mg": "beta 2/2/4, FMG start (threshold 1.0)"},
+            "order6_reference_cd": ref, "runs": out}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +515,10 @@ def main() -> int:
     ap.add_argument("--sphere-quantiles", type=float, nargs="+", default=[0.3, 0.6, 0.9])
     ap.add_argument("--sphere-nmin", type=int, default=4)
     ap.add_argument("--sphere-ref-cd", type=float, default=0.0)
+    ap.add_argument("--sphere-multistage", action="store_true", help="multi-stage vs single-stage adaptation")
+    ap.add_argument("--sphere-tau-max", type=float, default=2.761e-2)
+    ap.add_argument("--sphere-max-cycles", type=int, default=40000)
+    ap.add_argument("--sphere-nmax", type=int, default=6)
     ap.add_argument("--compare-s", type=float, default=40.0)
     ap.add_argument("--compare-rk-chunk", type=int, default=1000)
     ap.add_argument("--compare-fas-chunk", type=int, default=20)
@@ -467,6 +545,9 @@ def main() -> int:
         return 0
     if args.sphere_adapt:
         print(json.dumps(sphere_adapt_bench(args)), flush=True)
+        return 0
+    if args.sphere_multistage:
+        print(json.dumps(sphere_multistage_bench(args)), flush=True)
         return 0
 
     import numpy as np

@@ -384,7 +384,8 @@ pmg_status pmg_remap_state(pmg_solver from, const double* Q_from_dev, pmg_solver
  * required order does not exceed stages[i+1]; the adapted problem is then solved to max |r| < final_tol.
  * Every solver and buffer of the stages is the library's and is freed before the call returns.
  *
- * mg: multigrid parameters of every stage's solver (level_caps must be NULL: the levels follow the orders).
+ * mg: multigrid parameters of every stage's solver (level_caps must be NULL: the levels follow the orders,
+ * from the solver's largest order down to n_coarse with Delta N = 1).
  * Outputs (caller-owned): Q_out_dev (device) receives the final state as [5][nn] in its first 5*nn doubles,
  * with nn <= capacity_nodes; out_orders[K*3], out_nodes (= nn), reports[n_stages] of which *n_reports are
  * written, final_cycles and final_res (nullable).  PMG_ERR_NOT_CONVERGED when the final solve stops at
@@ -399,6 +400,7 @@ typedef struct {
   double conv;             /* each stage is converged to conv * tau_max before its estimate (0.1) */
   double final_tol;        /* tolerance of the final solve on the adapted orders */
   int32_t max_cycles;      /* cap on the V-cycles of each solve */
+  int32_t n_coarse;        /* coarsest multigrid order of every stage's solver (the paper's N_coarse; <= 1: 1) */
 } pmg_multistage_params;
 
 typedef struct {

@@ -225,7 +225,8 @@ class AdaptParams(C.Structure):
 
 class MultistageParams(C.Structure):
     _fields_ = [("stages", C.POINTER(C.c_int32)), ("n_stages", C.c_int32), ("adapt", AdaptParams),
-                ("conv", C.c_double), ("final_tol", C.c_double), ("max_cycles", C.c_int32)]
+                ("conv", C.c_double), ("final_tol", C.c_double), ("max_cycles", C.c_int32),
+                ("n_coarse", C.c_int32)]
 
 
 class StageReport(C.Structure):
@@ -280,7 +281,7 @@ def remap_state(src: "Solver", Q_src, dst: "Solver", Q_dst=None):
 def adapt_multistage(ctx: "Context", mesh: "Mesh", orders, phys, mg: "MG", stages, tau_max: float,
                      n_max=(7, 7, 7), n_min: int = 1, jump_rule: int = 1, wall_conforming: bool = False,
                      conv: float = 0.1, final_tol: float = 1e-8, max_cycles: int = 100,
-                     raise_not_converged: bool = True):
+                     raise_not_converged: bool = True, n_coarse: int = 1):
     """Multi-stage adaptation from free stream on the first stage's ``orders`` (pmg_adapt_multistage).
     Returns (orders (K, 3), state [5][nn] as a torch tensor, per-stage reports, final cycles, final residual)."""
     import torch
@@ -294,7 +295,7 @@ def adapt_multistage(ctx: "Context", mesh: "Mesh", orders, phys, mg: "MG", stage
     ph = physics_struct(phys)
     prm = MultistageParams(st.ctypes.data_as(C.POINTER(C.c_int32)), len(st),
                            adapt_params(tau_max, n_max, n_min, jump_rule, wall_conforming, 0), float(conv),
-                           float(final_tol), int(max_cycles))
+                           float(final_tol), int(max_cycles), int(n_coarse))
     out = np.zeros((K, 3), dtype=np.int32)
     nn = C.c_int64()
     reps = (StageReport * len(st))()
