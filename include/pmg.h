@@ -382,7 +382,8 @@ pmg_status pmg_remap_state(pmg_solver from, const double* Q_from_dev, pmg_solver
  * and the orders are selected by pmg_adapt_orders with n_cap = stages[i+1] (none on the last stage); the state
  * is carried over (pmg_remap_state).  The adaptation ends at the last stage or at the first one whose largest
  * required order does not exceed stages[i+1]; the adapted problem is then solved to max |r| < final_tol.
- * Every solver and buffer of the stages is the library's and is freed before the call returns.
+ * Every solver and buffer of the stages is the library's and is freed before the call returns.  The work runs
+ * on 'stream'; the call returns once it has completed.
  *
  * mg: multigrid parameters of every stage's solver (level_caps must be NULL: the levels follow the orders,
  * from the solver's largest order down to n_coarse with Delta N = 1).
