@@ -203,3 +203,25 @@ def test_full_size_bench_step(ctx):
     m = ~np.isnan(to)
     _, sc = o.operator_scale(wl.orders, wl.Q)
     assert np.abs(tau[m] - to[m]).max() <= (1e-12 + stol) * sc.max()
+
+
+@pytest.mark.parametrize("which", ["plate", "ogrid"])
+def test_full_size_fas_fixed_point(ctx, which):
+    """Configurations 2 and 3 at full size (the O-grid's random orders 1..7 include 8-node elements): with the
+    source S = A(Q) every level's FAS problem is already solved, so one V-cycle leaves Q unchanged up to the
+    round-off its operator evaluations carry (a property that holds at any size; the oracle gives the scales)."""
+    from oracle import oracle as O
+    from paper_1806_11456_amd import pmg
+    wl = I.config_plate() if which == "plate" else I.config_ogrid()
+    mg = dict(beta_pre=1, beta_post=1, beta_coarse=2)
+    s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys, pmg.MG(**mg))
+    Q = s.tensor(wl.Q)
+    S = -s.residual(Q, None)  # R = 0 - A(Q)
+    Q1 = Q.clone()
+    s.vcycle(Q1, S, n_cycles=1)
+    o = O.Oracle(wl.mesh, wl.phys)
+    nlev = int(wl.orders.max())
+    # per level: 2 sweeps x 3 stages, the FAS source and the restricted residual (4 sweeps on the coarsest)
+    n_evals = 2 * (nlev * 8 + 12)
+    stol = state_tol(o, wl, n_evals)
+    check(np_(Q1), wl.Q, None, stol, f"{which} FAS fixed point")
