@@ -105,3 +105,16 @@ def test_wall_force_without_walls_and_batches(ctx):
                   [pl.phys, pl.phys], pmg.MG())
     with pytest.raises(pmg.PmgError, match="single-problem"):
         b.wall_force(b.empty())
+
+
+def test_wall_force_after_state_changed_in_place(ctx):
+    """A call that leaves the traces of Q cached (a residual), then Q changed in place by the caller: the force
+    is that of the new state (the traces are formed again)."""
+    wl, Q = _force_case("plate8x4")
+    s, o = pair(ctx, wl)
+    Qt = s.tensor(Q)
+    s.residual(Qt)
+    Qt.mul_(1.01)
+    Fg = s.wall_force(Qt)
+    Fo, sc = o.wall_force(wl.orders, Q * 1.01)
+    assert np.all(np.abs(Fg - Fo) <= 1e-12 * sc), (Fg, Fo)
