@@ -89,7 +89,7 @@ def main() -> int:
     md = os.path.splitext(args.out)[0] + ".md"
     with open(md, "w") as f:
         f.write(f"# HBM traffic of {args.kernel} (rocprofv3 FETCH_SIZE / WRITE_SIZE)\n\n")
-        f.write(f"Command (repository root, on the GPU box):\n\n    {args.command}\n\n")
+        f.write(f"Command (repository root, on one MI355X):\n\n    {args.command}\n\n")
         f.write(f"Calibration: a plain device copy of {args.copy_mib} MiB reads FETCH_SIZE = {f_copy:.0f} KiB and "
                 f"WRITE_SIZE = {w_copy:.0f} KiB; scale factors {fs:.3f} (fetch) and {ws:.3f} (write).\n\n")
         f.write(f"{args.kernel}: {n} dispatches, average FETCH_SIZE {f_avg:.1f} KiB, WRITE_SIZE {w_avg:.1f} KiB; "
