@@ -501,7 +501,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--beta", type=int, nargs=3, default=[2, 2, 4], metavar=("PRE", "POST", "COARSE"))
     ap.add_argument("--residual-loops", type=int, default=200)
-    ap.add_argument("--cpu-evals", type=int, default=6)
+    ap.add_argument("--cpu-evals", type=int, default=15)  # about 13 s of one CPU thread
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
