@@ -40,3 +40,15 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pmg, "_lib", None)
     with pytest.raises(RuntimeError):
         pmg.lib()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: asked for more it exits with status 2 and says so, before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
