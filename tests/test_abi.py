@@ -52,3 +52,41 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every parameter struct the binding passes by pointer has the header's size and field offsets: a C program
+    compiled against include/pmg.h prints them, the ctypes mirrors must agree field by field."""
+    import ctypes
+    import os
+    import shutil
+    import subprocess
+
+    from paper_1806_11456_amd import pmg
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    mirrors = {"pmg_physics": pmg.Physics, "pmg_mg_params": pmg.MGParams, "pmg_adapt_params": pmg.AdaptParams,
+               "pmg_multistage_params": pmg.MultistageParams, "pmg_stage_report": pmg.StageReport}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pmg.h"', "int main(void) {"]
+    for cname, mirror in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in mirror._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            name, key, val = ln.split()
+            got[(name, key)] = int(val)
+    for cname, mirror in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(mirror), cname
+        for field, _ in mirror._fields_:
+            assert got[(cname, field)] == getattr(mirror, field).offset, (cname, field)
