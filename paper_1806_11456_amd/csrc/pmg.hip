@@ -1719,6 +1719,7 @@ pmg_status pmg_batch_norms(pmg_solver s, const double* Q_dev, const double* S_de
 pmg_status pmg_timestep(pmg_solver s, const double* Q_dev, double* dt_host, void* stream) {
   return guard([&] {
     REQUIRE(s && Q_dev && dt_host, "NULL argument");
+    traces_stale(s);
     hipStream_t st = (hipStream_t)stream;
     timestep(s, *s->top, Q_dev, st);
     std::vector<double> v = read_slots(s, SLOT_DT, st);
@@ -1871,6 +1872,7 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
                      double* res_inf_out, void* stream) {
   pmg_status rc = guard([&] {
     REQUIRE(s && Q_dev && max_cycles >= 0, "bad argument");
+    traces_stale(s);  // the caller may have changed Q in place since the last evaluation
     hipStream_t st = (hipStream_t)stream;
     const bool mixed = s->mg.precision == 1;
     const int patience = s->mg.mixed_patience > 0 ? s->mg.mixed_patience : 4;
@@ -1933,6 +1935,7 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
                            int32_t* cycles_out, double* res_inf_out, void* stream) {
   pmg_status rc = guard([&] {
     REQUIRE(s && Q_dev && max_cycles >= 0, "bad argument");
+    traces_stale(s);  // the caller may have changed Q in place since the last evaluation
     hipStream_t st = (hipStream_t)stream;
     const int n = s->nprob;
     const bool mixed = s->mg.precision == 1;
@@ -1984,8 +1987,6 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
 pmg_status pmg_solve_stats(pmg_solver s, int32_t* fp32_cycles) {
   return guard([&] {
     REQUIRE(s && fp32_cycles, "NULL argument");
-    traces_stale(s);
-    traces_stale(s);
     for (int p = 0; p < s->nprob; p++) fp32_cycles[p] = s->fp32_cycles[p];
   });
 }
@@ -2031,12 +2032,13 @@ struct pmg_server_s {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<std::shared_ptr<ServerReq>> queue;
-  std::vector<std::shared_ptr<ServerReq>> resident;
+  std::vector<std::shared_ptr<ServerReq>> resident;  // the worker thread's own list (no lock)
   std::map<uint64_t, std::shared_ptr<ServerReq>> all;
+  // the fields below are read and written under mu
   double used = 0.0, peak = 0.0;
   uint64_t next_ticket = 1;
   int64_t completed = 0, iterations = 0;
-  int max_resident = 0;
+  int n_resident = 0, max_resident = 0;  // published by the worker after each change of 'resident'
   bool stop = false;
   std::string fatal;
   std::thread worker;
@@ -2095,7 +2097,11 @@ static void server_loop(pmg_server_s* sv) {
         continue;
       }
       sv->resident.push_back(r);
-      sv->max_resident = std::max(sv->max_resident, (int)sv->resident.size());
+    }
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->n_resident = (int)sv->resident.size();
+      sv->max_resident = std::max(sv->max_resident, sv->n_resident);
     }
     if (sv->resident.empty()) continue;
     // one iteration: the decided cycle, then the residual norm, for every resident request
@@ -2116,7 +2122,6 @@ static void server_loop(pmg_server_s* sv) {
       }
     }
     for (hipStream_t st : sv->streams) (void)hipStreamSynchronize(st);
-    sv->iterations++;
     std::vector<std::shared_ptr<ServerReq>> keep;
     for (auto& r : sv->resident) {
       int status = r->status >= 0 ? r->status : -1;
@@ -2138,9 +2143,14 @@ static void server_loop(pmg_server_s* sv) {
       else keep.push_back(r);
     }
     sv->resident.swap(keep);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->iterations++;
+    sv->n_resident = (int)sv->resident.size();
   }
   for (auto& r : sv->resident) server_retire(sv, r, PMG_ERR_BUSY);
   sv->resident.clear();
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->n_resident = 0;
 }
 
 extern "C" {
@@ -2253,7 +2263,7 @@ pmg_status pmg_server_stats(pmg_server sv, int* resident, int* queued, int64_t* 
   return guard([&] {
     REQUIRE(sv, "NULL server");
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (resident) *resident = (int)sv->resident.size();
+    if (resident) *resident = sv->n_resident;
     if (queued) *queued = (int)sv->queue.size();
     if (completed) *completed = sv->completed;
     if (iterations) *iterations = sv->iterations;
