@@ -434,6 +434,16 @@ pmg_status pmg_adapt_multistage(pmg_ctx ctx, pmg_mesh mesh, const int32_t* order
  */
 pmg_status pmg_wall_force(pmg_solver s, const double* Q_dev, double* force_host, void* stream);
 
+/*
+ * Drag and lift coefficients of a wall force (Secs. 4.1 and 4.2): with the non-dimensional far field
+ * rho_inf = 1, |v_inf| = 1 the dynamic pressure is 1/2, so C = 2 F / A_ref; drag along v_inf = (1, 0, 0),
+ * lift along y.  force_host[6] (host): the output of pmg_wall_force (pressure part x, y, z, then viscous
+ * part x, y, z; each coefficient takes the sum of both parts).  area_ref > 0 (for the unit sphere pi).
+ * coef_host[4] (host, out): C_d, C_l, then the pressure part of C_d and its viscous part.  Host arithmetic
+ * only; PMG_ERR_INVALID_ARG for NULL pointers or a non-positive area.
+ */
+pmg_status pmg_force_coefficients(const double* force_host, double area_ref, double* coef_host);
+
 #ifdef __cplusplus
 }
 #endif

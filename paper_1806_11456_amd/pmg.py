@@ -24,7 +24,7 @@ EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_crea
            "pmg_solver_create", "pmg_solver_destroy", "pmg_state_layout", "pmg_init_freestream", "pmg_residual",
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
            "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_profile_stride", "pmg_adapt_orders",
-           "pmg_remap_state", "pmg_adapt_multistage", "pmg_wall_force", "pmg_batch_create",
+           "pmg_remap_state", "pmg_adapt_multistage", "pmg_wall_force", "pmg_force_coefficients", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
            "pmg_level_tiles", "pmg_solve_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
            "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy", "pmg_tau_nodal",
@@ -115,6 +115,7 @@ def lib():
                                    I32]
     L.pmg_remap_state.argtypes = [P, V, P, V, V]
     L.pmg_wall_force.argtypes = [P, V, D, V]
+    L.pmg_force_coefficients.argtypes = [D, C.c_double, D]
     L.pmg_adapt_multistage.argtypes = [P, P, I32, C.POINTER(Physics), C.POINTER(MGParams),
                                        C.POINTER(MultistageParams), V, C.c_int64, I32, I64,
                                        C.POINTER(StageReport), I32, I32, D, V]
@@ -265,10 +266,13 @@ def adapt_params(tau_max, n_max=(7, 7, 7), n_min=1, jump_rule=1, wall_conforming
 
 
 def force_coefficients(F, area: float):
-    """(drag, lift) coefficients of a wall force F (6 values, pressure and viscous parts) with rho_inf = |v_inf| =
-    1, the drag along v_inf = (1, 0, 0) and the lift along y: 2 F / area."""
-    tot = np.asarray(F[:3]) + np.asarray(F[3:6])
-    return 2.0 * tot[0] / area, 2.0 * tot[1] / area
+    """(drag, lift) coefficients of a wall force F (the 6 values of Solver.wall_force), pmg_force_coefficients."""
+    f = np.ascontiguousarray(F, dtype=np.float64)
+    assert f.shape == (6,)
+    c = np.zeros(4)
+    _check(lib().pmg_force_coefficients(f.ctypes.data_as(C.POINTER(C.c_double)), float(area),
+                                        c.ctypes.data_as(C.POINTER(C.c_double))))
+    return float(c[0]), float(c[1])
 
 
 def remap_state(src: "Solver", Q_src, dst: "Solver", Q_dst=None):
