@@ -184,15 +184,29 @@ void ora_tau_nodal(or_problem* P, const int32_t* ord, const or_mg_params* prm, d
   free(tau_map);
 }
 
-int ora_solve(or_problem* P, const int32_t* ord, int nlev, const int32_t* caps, const or_mg_params* prm, double* Q,
-              const double* S, double tol, int max_cycles, double* res_out, double* history) {
+/* Steady solve; reps (nullable, 2 * nlev): smoothing blocks of the last visit of each level (pre, post; level
+   index 0 = coarsest); fmg_cycles (nullable, nlev): V-cycles the FMG start ran on each level. */
+int ora_solve_ex(or_problem* P, const int32_t* ord, int nlev, const int32_t* caps, const or_mg_params* prm, double* Q,
+                 const double* S, double tol, int max_cycles, double* res_out, double* history, int32_t* reps,
+                 int32_t* fmg_cycles) {
   int* c = malloc(sizeof(int) * nlev);
   for (int l = 0; l < nlev; l++) c[l] = caps[l];
   or_mg* mg = or_mg_create(P, ord, nlev, c, -1);
+  mg->reps = calloc(2 * nlev, sizeof(int));
+  mg->fmg_cycles = calloc(nlev, sizeof(int));
   int cyc = or_mg_solve(P, mg, Q, S, tol, max_cycles, prm, res_out, history);
+  for (int l = 0; l < nlev; l++) {
+    if (reps) { reps[2 * l] = mg->reps[2 * l]; reps[2 * l + 1] = mg->reps[2 * l + 1]; }
+    if (fmg_cycles) fmg_cycles[l] = mg->fmg_cycles[l];
+  }
   or_mg_destroy(mg);
   free(c);
   return cyc;
+}
+
+int ora_solve(or_problem* P, const int32_t* ord, int nlev, const int32_t* caps, const or_mg_params* prm, double* Q,
+              const double* S, double tol, int max_cycles, double* res_out, double* history) {
+  return ora_solve_ex(P, ord, nlev, caps, prm, Q, S, tol, max_cycles, res_out, history, NULL, NULL);
 }
 
 /* Test hook: one RK3 sweep of the linear residual R(Q) = lambda Q. */

@@ -165,6 +165,7 @@ void or_mg_destroy(or_mg* mg) {
     free(mg->Q[l]); free(mg->Q0[l]); free(mg->S[l]); free(mg->r[l]); free(mg->Sphys[l]);
   }
   free(mg->L); free(mg->Q); free(mg->Q0); free(mg->S); free(mg->r); free(mg->Sphys); free(mg->caps);
+  free(mg->reps); free(mg->fmg_cycles);
   free(mg);
 }
 
@@ -193,17 +194,21 @@ static void pre_smooth(const or_problem* P, or_mg* mg, int l, const or_mg_params
     or_smooth(P, L, mg->Q[l], mg->S[l], l == 0 ? prm->beta_coarse : prm->beta_pre);
     or_residual(P, L, 0, mg->Q[l], mg->S[l], Rfine);
     *rnorm_pre = or_norm_inf(Rfine, n);
+    if (mg->reps) mg->reps[2 * l] = 1;
     return;
   }
   /* pre-smoothing stops once ||r^P|| < eta ||I r^P|| (residual checked in the next coarser representation) */
   const or_level* Lc = mg->L[l - 1];
   double* rc = malloc(sizeof(double) * 5 * Lc->nn);
+  int blocks = 0;
   for (int rep = 0; rep < prm->max_repeats; rep++) {
     or_smooth(P, L, mg->Q[l], mg->S[l], prm->beta_pre);
+    blocks++;
     or_residual(P, L, 0, mg->Q[l], mg->S[l], Rfine);
     or_restrict(P, L, Lc, Rfine, rc);
     if (or_norm_inf(Rfine, n) < prm->eta * or_norm_inf(rc, 5 * Lc->nn)) break;
   }
+  if (mg->reps) mg->reps[2 * l] = blocks;
   *rnorm_pre = or_norm_inf(Rfine, n);
   free(rc);
 }
@@ -212,16 +217,20 @@ static void post_smooth(const or_problem* P, or_mg* mg, int l, const or_mg_param
   const or_level* L = mg->L[l];
   if (!prm->tuning) {
     or_smooth(P, L, mg->Q[l], mg->S[l], prm->beta_post);
+    if (mg->reps) mg->reps[2 * l + 1] = 1;
     return;
   }
   /* post-smoothing stops once ||r_post|| <= ||r_pre|| */
   int64_t n = 5 * L->nn;
   double* R = malloc(sizeof(double) * n);
+  int blocks = 0;
   for (int rep = 0; rep < prm->max_repeats; rep++) {
     or_smooth(P, L, mg->Q[l], mg->S[l], prm->beta_post);
+    blocks++;
     or_residual(P, L, 0, mg->Q[l], mg->S[l], R);
     if (or_norm_inf(R, n) <= rnorm_pre) break;
   }
+  if (mg->reps) mg->reps[2 * l + 1] = blocks;
   free(R);
 }
 
@@ -305,6 +314,7 @@ int or_mg_solve(const or_problem* P, or_mg* mg, double* Q, const double* S, doub
         if (r < prm->fmg_threshold || cycles >= max_cycles) break;
         vcycle(P, mg, l, l, prm, NULL, 0);
         cycles++;
+        if (mg->fmg_cycles) mg->fmg_cycles[l]++;
       }
       free(R);
       or_prolong(P, mg->L[l], mg->L[l + 1], mg->Q[l], mg->Q[l + 1]);

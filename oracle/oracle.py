@@ -81,6 +81,9 @@ def lib():
         L.ora_operator_scale.argtypes = [P, I32, C.c_int, D, D, D]
         L.ora_solve.restype = C.c_int
         L.ora_solve.argtypes = [P, I32, C.c_int, I32, C.POINTER(MGParams), D, D, C.c_double, C.c_int, D, D]
+        L.ora_solve_ex.restype = C.c_int
+        L.ora_solve_ex.argtypes = [P, I32, C.c_int, I32, C.POINTER(MGParams), D, D, C.c_double, C.c_int, D, D, I32,
+                                   I32]
         _lib = L
     return _lib
 
@@ -297,3 +300,21 @@ class Oracle:
         cyc = lib().ora_solve(self.h, _i32(orders), len(caps), _i32(caps), C.byref(p), _d(Q), Sp, float(tol),
                               int(max_cycles), _d(res), _d(hist))
         return Q, int(cyc), float(res[0]), hist[:cyc + 1]
+
+    def solve_record(self, orders, Q, S=None, caps=None, tol=1e-9, max_cycles=100, **prm):
+        """solve() that also returns the smoothing blocks of the last visit of each level (reps[l] = (pre, post),
+        level 0 the coarsest) and the V-cycles the FMG start ran on each level."""
+        orders = self._ord(orders)
+        if caps is None:
+            caps = list(range(int(orders.max()), 0, -1))
+        caps = np.asarray(caps, dtype=np.int32)
+        Q = np.array(Q, dtype=np.float64, copy=True)
+        Sp = _d(_f64(S)) if S is not None else None
+        p = mg_params(**prm)
+        res = np.zeros(1)
+        hist = np.zeros(max_cycles + 1)
+        reps = np.zeros((len(caps), 2), dtype=np.int32)
+        fmg = np.zeros(len(caps), dtype=np.int32)
+        cyc = lib().ora_solve_ex(self.h, _i32(orders), len(caps), _i32(caps), C.byref(p), _d(Q), Sp, float(tol),
+                                 int(max_cycles), _d(res), _d(hist), _i32(reps), _i32(fmg))
+        return Q, int(cyc), float(res[0]), reps, fmg

@@ -23,6 +23,10 @@ typedef struct {
   /* optional copy of the pointwise truncation error [5][nn] of the level whose cap is tau_nodal_cap */
   double* tau_nodal;
   int tau_nodal_cap;
+  /* optional records for the tests: smoothing blocks of the last visit of each level (pre at [2 l], post at
+     [2 l + 1]; with fixed sweeps each phase counts one block), and V-cycles the FMG start ran on each level */
+  int* reps;
+  int* fmg_cycles;
 } or_mg;
 
 void or_residual(const or_problem* P, const or_level* L, int isolated, const double* Q, const double* S, double* R);
