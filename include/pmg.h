@@ -435,6 +435,18 @@ pmg_status pmg_adapt_multistage(pmg_ctx ctx, pmg_mesh mesh, const int32_t* order
 pmg_status pmg_wall_force(pmg_solver s, const double* Q_dev, double* force_host, void* stream);
 
 /*
+ * pmg_wall_force for callers that cannot allocate device memory (code under stream or graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same force, bit for bit, computed without any
+ * hipMalloc / hipFree or allocating library call.  Its block partials and their sum live in a static device
+ * array of the library (one per GPU, 384 KiB, held until the process ends); the caller passes the solver,
+ * Q_dev and force_host exactly as for pmg_wall_force.  At most 8192 x 256 = 2,097,152 wall nodes on the
+ * finest level (PMG_ERR_INVALID_ARG beyond).  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (other threads, other streams) race and must be serialised by the caller.  Returns once the stream
+ * has completed.
+ */
+pmg_status pmg_wall_force_noalloc(pmg_solver s, const double* Q_dev, double* force_host, void* stream);
+
+/*
  * Drag and lift coefficients of a wall force (Secs. 4.1 and 4.2): with the non-dimensional far field
  * rho_inf = 1, |v_inf| = 1 the dynamic pressure is 1/2, so C = 2 F / A_ref; drag along v_inf = (1, 0, 0),
  * lift along y.  force_host[6] (host): the output of pmg_wall_force (pressure part x, y, z, then viscous

@@ -28,6 +28,14 @@
 #include "kernels_mg.inc"
 #include "host_basis.inc"
 
+// Scratch of the allocation-free entry points (pmg_wall_force_noalloc): one copy per device, held until the
+// process ends.  Block partials of the wall-force sum (PMG_SCRATCH_BLOCKS blocks of 256 wall nodes, 6 values
+// each) followed by the 6 summed values.  Host code reaches it only through the address that pmg_ctx_create
+// takes with hipGetSymbolAddress (pmg_ctx_s::scratch).
+#define PMG_SCRATCH_BLOCKS 8192
+#define PMG_SCRATCH_DOUBLES (6 * PMG_SCRATCH_BLOCKS + 8)
+static __device__ __align__(256) double scratch[PMG_SCRATCH_DOUBLES];
+
 // ------------------------------------------------------------------------------------------------
 // Errors
 // ------------------------------------------------------------------------------------------------
@@ -110,6 +118,7 @@ inline int pack3(int a, int b, int c) { return a | (b << 8) | (c << 16); }
 struct pmg_ctx_s {
   int device = 0;
   int lds_max = 65536;  // LDS bytes one workgroup may allocate on the device
+  double* scratch = nullptr;  // device address of this device's copy of 'scratch' (hipGetSymbolAddress)
   DevArena arena;
   double* T[2] = {nullptr, nullptr};  // transfer tables per family
   std::map<std::string, int> tile_cache;  // autotuned tile targets keyed by level structure
@@ -1450,6 +1459,11 @@ static pmg_solver_s* create_solver(pmg_ctx ctx, const std::vector<const pmg_mesh
   s->d_red = s->arena.alloc<unsigned long long>((size_t)NSLOTS * n);
   s->d_part = s->arena.alloc<unsigned long long>((size_t)K);
   s->top = build_level(s.get(), s->orders);
+  if (!s->top->wall_mn.empty()) {
+    // quadrature lists of the no-slip walls of the finest level (read by the wall-force entry points)
+    s->top->d_wall_mn = s->top->arena.upload(s->top->wall_mn);
+    s->top->d_wall_w = s->top->arena.upload(s->top->wall_w);
+  }
   std::vector<int> caps;
   if (mg && mg->n_levels > 0 && mg->level_caps) {
     caps.assign(mg->level_caps, mg->level_caps + mg->n_levels);
@@ -1481,7 +1495,7 @@ static pmg_solver_s* create_solver(pmg_ctx ctx, const std::vector<const pmg_mesh
 // hierarchies are built on first use and are not included).
 // ------------------------------------------------------------------------------------------------
 struct LevelCount {
-  double nn = 0, nf = 0, nm = 0, nfaces = 0, ntiles = 0;
+  double nn = 0, nf = 0, nm = 0, nfaces = 0, ntiles = 0, nwall = 0;
 };
 
 static LevelCount count_level(const pmg_mesh_s* m, const std::vector<int>& ord, const std::vector<int>& eprob) {
@@ -1507,6 +1521,7 @@ static LevelCount count_level(const pmg_mesh_s* m, const std::vector<int>& ord, 
       }
       c.nm += (double)ms * mt;
       c.nfaces += 1;
+      if (g < 0 && m->bc[6 * e + f] == 1) c.nwall += (double)ms * mt;
     }
   }
   for (auto& kv : buckets) {
@@ -1528,6 +1543,7 @@ static double level_bytes(const LevelCount& c, int64_t K, int prec, bool top) {
   double b = 4.0 * (3 * K + (K + 1) + 6 * K + c.nn + c.nm + c.nm / 64.0 + 2) + sizeof(FaceRec) * c.nfaces;
   b += 8.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0) + 2 * c.nn);  // FP64 geometry
   if (top) b += 8.0 * (5 * c.nf + 4 * c.nf + 12 * c.nn + 12 * c.nf + 5 * c.nf + 4 * c.nf);  // shared work arrays
+  if (top) b += 12.0 * c.nwall;  // wall quadrature lists
   if (prec == PREC_F32) b += 4.0 * (9 * c.nn + c.nn + c.nn + 3 * c.nf + 4 * std::max(c.nm, 1.0));
   b += 3 * 4.0 * K + 32.0 * c.ntiles + 4.0 * (c.nm / 64.0 + 2);  // element tiles (+ offsets), face-tile problems
   b += 8.0 * c.nf + 16.0 * (c.nm / 64.0 + 2);  // interface links (state, mortar node), face-tile list and records
@@ -1597,6 +1613,12 @@ pmg_status pmg_ctx_create(int hip_device, pmg_ctx* out) {
       c->T[fam] = c->arena.upload(T);
     }
     HIPCHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_tab), B, sizeof(B)));
+    // this device's copy of the static scratch array of the allocation-free entry points: host code uses
+    // only the address returned here, never the array's name
+    void* sp = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)));
+    REQUIRE(sp != nullptr, "no device address for the scratch array");
+    c->scratch = (double*)sp;
     *out = c.release();
   });
 }

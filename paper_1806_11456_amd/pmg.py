@@ -24,7 +24,8 @@ EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_crea
            "pmg_solver_create", "pmg_solver_destroy", "pmg_state_layout", "pmg_init_freestream", "pmg_residual",
            "pmg_timestep", "pmg_smooth", "pmg_level_info", "pmg_restrict", "pmg_prolong", "pmg_vcycle",
            "pmg_solve", "pmg_tau_estimate", "pmg_profile_enable", "pmg_profile_read", "pmg_profile_stride", "pmg_adapt_orders",
-           "pmg_remap_state", "pmg_adapt_multistage", "pmg_wall_force", "pmg_force_coefficients", "pmg_batch_create",
+           "pmg_remap_state", "pmg_adapt_multistage", "pmg_wall_force", "pmg_wall_force_noalloc",
+           "pmg_force_coefficients", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
            "pmg_level_tiles", "pmg_solve_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
            "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy", "pmg_tau_nodal",
@@ -115,6 +116,7 @@ def lib():
                                    I32]
     L.pmg_remap_state.argtypes = [P, V, P, V, V]
     L.pmg_wall_force.argtypes = [P, V, D, V]
+    L.pmg_wall_force_noalloc.argtypes = [P, V, D, V]
     L.pmg_force_coefficients.argtypes = [D, C.c_double, D]
     L.pmg_adapt_multistage.argtypes = [P, P, I32, C.POINTER(Physics), C.POINTER(MGParams),
                                        C.POINTER(MultistageParams), V, C.c_int64, I32, I64,
@@ -386,6 +388,13 @@ class Solver:
         """Force on the no-slip walls (pmg_wall_force): pressure part x, y, z, then viscous part x, y, z."""
         F = np.zeros(6)
         _check(lib().pmg_wall_force(self.h, _ptr(Q), F.ctypes.data_as(C.POINTER(C.c_double)), _stream()))
+        return F
+
+    def wall_force_noalloc(self, Q) -> np.ndarray:
+        """The same force without device allocation (pmg_wall_force_noalloc): partials in the library's static
+        per-GPU scratch; calls that overlap on one GPU race."""
+        F = np.zeros(6)
+        _check(lib().pmg_wall_force_noalloc(self.h, _ptr(Q), F.ctypes.data_as(C.POINTER(C.c_double)), _stream()))
         return F
 
     def timestep(self, Q) -> float:
