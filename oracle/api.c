@@ -241,3 +241,11 @@ void ora_wall_force(or_problem* P, const int32_t* ord, const double* Q, double* 
   or_wall_force(P, L, Q, out);
   or_level_destroy(L);
 }
+
+/* operator evaluations made since the last call (every level, isolated or not) */
+extern long long or_n_evals;
+int64_t ora_take_eval_count(void) {
+  int64_t n = (int64_t)or_n_evals;
+  or_n_evals = 0;
+  return n;
+}

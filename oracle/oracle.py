@@ -79,6 +79,8 @@ def lib():
         L.ora_gradient.argtypes = [P, I32, C.c_int, D, D]
         L.ora_wall_force.argtypes = [P, I32, D, D]
         L.ora_operator_scale.argtypes = [P, I32, C.c_int, D, D, D]
+        L.ora_take_eval_count.restype = C.c_int64
+        L.ora_take_eval_count.argtypes = []
         L.ora_solve.restype = C.c_int
         L.ora_solve.argtypes = [P, I32, C.c_int, I32, C.POINTER(MGParams), D, D, C.c_double, C.c_int, D, D]
         L.ora_solve_ex.restype = C.c_int
@@ -208,6 +210,11 @@ class Oracle:
         A = np.zeros_like(Q)
         lib().ora_operator(self.h, _i32(self._ord(orders)), int(isolated), _d(Q), _d(A))
         return A
+
+    @staticmethod
+    def take_eval_count() -> int:
+        """Operator evaluations the oracle made since the previous call (all levels)."""
+        return int(lib().ora_take_eval_count())
 
     def operator_scale(self, orders, Q, isolated=False):
         """(A, scale): scale[v, node] = sum of |terms| entering A[v, node] (its round-off scale)."""

@@ -341,10 +341,19 @@ void or_gradient(const or_problem* P, const or_level* L, int isolated, const dou
   free(Ws);
 }
 
-/* A(Q); when 'scale' is given it receives, per node and variable, the sum of the magnitudes of the terms
- * that make up A (the round-off scale of that entry, divided by J like A itself). */
+/* A(Q); when 'scale' is given it receives, per node and variable, the round-off scale of that entry (divided
+ * by J like A itself): the sum over the terms that make it up of a bound on each term's magnitude.  A term
+ * that contracts a flux with a metric vector (J a^d in the volume, the scaled normal N on a face) is bounded
+ * by Cauchy-Schwarz, |sum_c F_c V_c| <= |V| sum_c |F_c|: the metric components are differences of products
+ * of the mapping's derivatives, so each carries rounding of the order of its vector's length, and a
+ * component that vanishes exactly (the z-components of an extruded mesh) still moves the entry by that
+ * much.  A face term also counts the magnitude of the numerical flux itself. */
+/* operator evaluations since the last reset (a count for the tests' round-off bars; no arithmetic) */
+long long or_n_evals = 0;
+
 void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const double* Q, double* A, double* scale) {
   const or_phys* ph = &P->ph;
+  or_n_evals++;
   const int64_t nn = L->nn, nf = L->nf;
   double* qf = malloc(sizeof(double) * 5 * nf);
   double* gW = malloc(sizeof(double) * 12 * nn);  /* grad W at nodes, [k*3 + c][nn] */
@@ -445,6 +454,26 @@ void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const 
       mortar_free(&m);
     }
 
+  /* round-off scale of each face term: |N| sum_c |(F^a - F^v)_c| of the own traces */
+  double* fsc = NULL;
+  if (scale) {
+    fsc = malloc(sizeof(double) * 5 * nf);
+    for (int64_t fi = 0; fi < nf; fi++) {
+      double q[5], g[4][3], Fa[3][5], Fv[3][5];
+      qvec(qf, nf, fi, q);
+      gvec(gf, nf, fi, g);
+      or_flux_adv(ph, q, Fa);
+      or_flux_visc(ph, q, g, Fv);
+      double N2 = 0.0;
+      for (int c = 0; c < 3; c++) N2 += L->Nout[c * nf + fi] * L->Nout[c * nf + fi];
+      for (int v = 0; v < 5; v++) {
+        double a = 0.0;
+        for (int c = 0; c < 3; c++) a += fabs(Fa[c][v] - Fv[c][v]);
+        fsc[v * nf + fi] = sqrt(N2) * a;
+      }
+    }
+  }
+
   /* (6) divergence of F^a - F^v: volume term + surface lift, divided by J */
   for (int64_t e = 0; e < L->K; e++) {
     int n[3];
@@ -453,6 +482,7 @@ void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const 
     int64_t o = L->off[e];
     int npe = n[0] * n[1] * n[2];
     double* Ft = malloc(sizeof(double) * 15 * npe); /* Ftilde^d_v at the nodes: [(d*5 + v)][p] */
+    double* Fs = malloc(sizeof(double) * 15 * npe); /* |J a^d| sum_c |F_c,v|: round-off scale of Ftilde^d_v */
     for (int p = 0; p < npe; p++) {
       double q[5], g[4][3], Fa[3][5], Fv[3][5];
       for (int v = 0; v < 5; v++) q[v] = Q[v * nn + o + p];
@@ -460,12 +490,19 @@ void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const 
         for (int c = 0; c < 3; c++) g[k][c] = gW[(k * 3 + c) * nn + o + p];
       or_flux_adv(ph, q, Fa);
       or_flux_visc(ph, q, g, Fv);
-      for (int d = 0; d < 3; d++)
+      for (int d = 0; d < 3; d++) {
+        double a2 = 0.0;
+        for (int c = 0; c < 3; c++) a2 += L->Ja[(d * 3 + c) * nn + o + p] * L->Ja[(d * 3 + c) * nn + o + p];
         for (int v = 0; v < 5; v++) {
-          double s = 0.0;
-          for (int c = 0; c < 3; c++) s += L->Ja[(d * 3 + c) * nn + o + p] * (Fa[c][v] - Fv[c][v]);
+          double s = 0.0, f = 0.0;
+          for (int c = 0; c < 3; c++) {
+            s += L->Ja[(d * 3 + c) * nn + o + p] * (Fa[c][v] - Fv[c][v]);
+            f += fabs(Fa[c][v] - Fv[c][v]);
+          }
           Ft[(d * 5 + v) * npe + p] = s;
+          Fs[(d * 5 + v) * npe + p] = sqrt(a2) * f;
         }
+      }
     }
     for (int k3 = 0; k3 < n[2]; k3++)
       for (int j = 0; j < n[1]; j++)
@@ -483,7 +520,7 @@ void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const 
               double Dh = -bd->D[m][id] * bd->w[m] / bd->w[id];
               for (int v = 0; v < 5; v++) {
                 s[v] += Dh * Ft[(d * 5 + v) * npe + pm];
-                sa[v] += fabs(Dh * Ft[(d * 5 + v) * npe + pm]);
+                sa[v] += fabs(Dh) * Fs[(d * 5 + v) * npe + pm];
               }
             }
             int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
@@ -493,7 +530,7 @@ void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const 
               double l = side ? bd->lp[id] : bd->lm[id];
               for (int v = 0; v < 5; v++) {
                 s[v] += l * Phi[v * nf + fi] / bd->w[id];
-                sa[v] += fabs(l * Phi[v * nf + fi] / bd->w[id]);
+                if (fsc) sa[v] += fabs(l / bd->w[id]) * (fabs(Phi[v * nf + fi]) + fsc[v * nf + fi]);
               }
             }
           }
@@ -502,8 +539,9 @@ void or_operator_ex(const or_problem* P, const or_level* L, int isolated, const 
             for (int v = 0; v < 5; v++) scale[v * nn + o + p] = sa[v] / fabs(L->J[o + p]);
         }
     free(Ft);
+    free(Fs);
   }
-  free(qf); free(gW); free(gf); free(Phi);
+  free(qf); free(gW); free(gf); free(Phi); free(fsc);
 }
 
 void or_operator(const or_problem* P, const or_level* L, int isolated, const double* Q, double* A) {

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from paper_1806_11456_amd import inputs as I
-from tests.gpu_util import check, gpu_pair, np_, small_cases
+from tests.gpu_util import check, derived_bar, gpu_pair, np_, small_cases
 
 pytestmark = pytest.mark.gpu
 
@@ -152,18 +152,23 @@ def test_multistage_matches_oracle(ctx):
         maps.append((N.copy(), tau.copy()))
         return select(mesh, N, tau, *a, **k)
 
+    total = [0]  # oracle operator evaluations so far
+
     def recording_solve(N, *a, **k):
         out = solve(N, *a, **k)
-        solved.append((np.array(N), out[0].copy()))
+        total[0] += o.take_eval_count()
+        solved.append((np.array(N), out[0].copy(), total[0]))
         return out
 
     A.select_orders, o.solve = recording, recording_solve
+    o.take_eval_count()
     try:
         Q0 = I.freestream_state(int(np.prod(first + 1, axis=1).sum()), wl.phys.mach)
         No, Qo, ro, co, reso = A.multistage(o, wl.mesh, first, stages, tau_max, n_max, n_min=n_min, rule=1,
                                             conv=1e-9, final_tol=1e-30, max_cycles=2, Q0=Q0, **mg)
     finally:
         A.select_orders, o.solve = select, solve
+    total[0] += o.take_eval_count()
     for P, tau in maps:
         assert _min_margin(P, tau, tau_max, n_max, n_min) > 1e-6
     # the first stage's carry-over lowers some elements and raises others (to the next stage's cap)
@@ -174,29 +179,21 @@ def test_multistage_matches_oracle(ctx):
     assert np.array_equal(Ng, No)
     assert len(rg) == len(ro) >= 2 and cg == co
 
-    def bars(N, Q, cycles):
-        """(state bar relative to |Q_v|, absolute bar of a residual entry) after 'cycles' V-cycles: every
-        operator evaluation adds the residual bar 1e-12 x (its round-off scale) times dt to the state, and a
-        residual of that state carries the operator's scale times both."""
-        _, sc = o.operator_scale(N, Q)
-        dt = o.timestep(N, Q)
-        qmax = np.abs(Q).max(axis=1)
-        qmax[1:4] = qmax[1:4].max()
-        n_evals = 3 * (2 + 2 + 4) * 6 * cycles
-        stol = 1e-12 * max(1.0, n_evals * max(dt * sc[v].max() / qmax[v] for v in range(5)))
-        return stol, (1e-12 + stol) * sc.max()
+    def bars(N, Q, n_evals):
+        """(per-variable state scale, bar of a residual entry) of a state after the oracle's n_evals operator
+        evaluations so far (an upper bound for each stage)."""
+        return derived_bar(o, I.Workload("stage", wl.mesh, N, wl.phys, Q), n_evals)
 
-    done = 0
     for i, (g, w) in enumerate(zip(rg, ro)):
         assert (g["stage_order"], g["cycles"], g["max_required"], bool(g["last"]), g["nodes_before"],
                 g["nodes_after"]) == (w["order"], w["cycles"], w["max_required"], w["last"], w["dof_before"],
                                       w["dof_after"])
-        done += w["cycles"] + 3 * (i > 0)
-        _, rbar = bars(*solved[i], done)
+        _, rbar = bars(*solved[i])
+        print(f"[parity] multi-stage stage {i} residual: error / bar {abs(g['res_inf'] - w['res']) / rbar:.2e}")
         assert abs(g["res_inf"] - w["res"]) <= rbar, (i, g["res_inf"], w["res"], rbar)
-    done += 3 + co
-    stol, rbar = bars(No, Qo, done)
-    check(np_(Qg), Qo, None, stol, "multi-stage final state")
+    ss, rbar = bars(No, Qo, total[0])
+    check(np_(Qg), Qo, ss, 1e-12, "multi-stage final state")
+    print(f"[parity] multi-stage final residual: error / bar {abs(resg - reso) / rbar:.2e}")
     assert abs(resg - reso) <= rbar
 
 

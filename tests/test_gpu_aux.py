@@ -10,8 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1806_11456_amd import inputs as I
-from tests.gpu_util import np_, small_cases
-from tests.test_gpu_parity import state_tol
+from tests.gpu_util import derived_bar, np_, small_cases
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +36,6 @@ def test_tau_nodal_parity(ctx, name, isolated):
     o = O.Oracle(wl.mesh, wl.phys)
     rng = np.random.default_rng(4)
     S = 0.1 * rng.uniform(-1, 1, size=wl.Q.shape)
-    _, sc = o.operator_scale(wl.orders, wl.Q)
     for d in range(3):
         pmax = int(wl.orders[:, d].max())
         for order in sorted({1, pmax - 1}):
@@ -45,11 +43,13 @@ def test_tau_nodal_parity(ctx, name, isolated):
                 continue
             Q = s.tensor(wl.Q)
             tg = np_(s.tau_nodal(Q, s.tensor(S), d=d, order=order, isolated=isolated))
+            o.take_eval_count()
             to, Qo = o.tau_nodal(wl.orders, wl.Q, S, d=d, cap=order, isolated=int(isolated), **MG)
-            stol = state_tol(o, wl, 3 * 3 * ((pmax - 1) * 2 + 2))
             # tau = S - A(I Q~): the operator bar plus the state bar carried through A
+            _, tbar = derived_bar(o, wl, o.take_eval_count())
             err = np.abs(tg - to).max()
-            assert err <= (1e-12 + stol) * sc.max(), (d, order, err, sc.max())
+            print(f"[parity] {name} tau nodal d={d} order={order} iso={isolated}: error / bar {err / tbar:.2e}")
+            assert err <= tbar, (d, order, err, tbar)
 
 
 def test_history_and_checkpoint(ctx, tmp_path):

@@ -477,3 +477,41 @@ def test_tau_nodal_reduces_to_tau_map(oracle_mod):
                 m = np.array([np.abs(tn[:, off[e]:off[e + 1]]).max() for e in range(w.mesh.K)])
                 assert np.array_equal(m, tau_map[:, d, cap - 1]), (iso, cap, d)
             assert np.array_equal(Q, Q3)
+
+
+# ------------------------------------------------------------------------------------------------------
+# Round-off scale of the operator (the parity bar of every residual entry)
+# ------------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["plate", "curved"])
+def test_roundoff_scale_bounds_geometry_rounding(oracle_mod, case):
+    """The per-variable round-off scale bounds the change of A when every geometry node moves by a rounding
+    error of the element's size (what an independent metric computation differs by): |dA_v| << eps s_v for
+    every variable on its own.  On the extruded plate the z-momentum entry moves by the rounding of the
+    metric vectors' vanishing z-components, far more than its own flux terms would suggest: its scale must
+    count the metric vectors' lengths (|J a^d| sum_c |F_c|), not the z-components alone."""
+    if case == "plate":
+        wl = I.config_plate(8, 4)
+    else:
+        base = I.box_mesh((3, 3, 3), (-1, -1, -1), (1, 1, 1), M=(2, 2, 2), wobble=0.12)
+        mesh, orders = I.reorient(base, 21, period=(2, 2, 2), orders=I.random_orders(base.K, 1, 7, 22))
+        ph = I.Physics(mach=0.3, reynolds=150.0, family=LG)
+        wl = I.Workload("curved", mesh, orders, ph, I.perturbed_freestream(int(I.node_offsets(orders)[-1]), 0.3,
+                                                                          0.02, 23))
+    o = oracle_mod.Oracle(wl.mesh, wl.phys)
+    A, sc = o.operator_scale(wl.orders, wl.Q)
+    assert (sc >= np.abs(A) * (1 - 1e-12)).all()
+    gn = wl.mesh.gnodes.copy()
+    rng = np.random.default_rng(3)
+    x0 = gn[:, :1, :1, :1, :]
+    size = np.abs(gn - x0).max(axis=(1, 2, 3), keepdims=True)
+    gn = gn + size * 2.0 ** -52 * rng.uniform(-1, 1, size=gn.shape)
+    import dataclasses
+    o2 = oracle_mod.Oracle(dataclasses.replace(wl.mesh, gnodes=gn), wl.phys)
+    A2 = o2.operator(wl.orders, wl.Q)
+    rel = np.abs(A2 - A).max(axis=1) / sc.max(axis=1)
+    print("change / scale per variable", rel)
+    assert (rel < 2e-13).all(), rel
+    if case == "plate":
+        # the z-momentum entry moves by more than 1e-12 of its own largest value: a bar built from the
+        # z-momentum's own magnitude would not hold
+        assert np.abs(A2 - A)[3].max() > 1e-12 * np.abs(A[3]).max()
