@@ -1,15 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the DGSEM / FAS p-multigrid hot path on one MI355X; prints one JSON line.
 
-Workload: the flat-plate boundary layer -- 64 x 32 x 1 hexahedra stretched toward the wall (ratio 1.1),
-quadratic mapping, orders N = (6, 6, 1) on Gauss nodes (200,704 DOF), Mach 0.2, Re_L = 1e5, no-slip
-adiabatic wall and far field, seeded perturbation of the far-field state.
+Headline workload (the largest single-GPU configuration): 64 independent steady problems solved together --
+random stretched boxes of 2k..20k hexahedra with a no-slip wall, orders iid in {2..5} per direction, Mach
+U[0.1, 0.4], Re U[1e2, 1e4] (63.9M DOF) -- in one batched solver: union mesh, one launch per kernel kind,
+captured V-cycle graphs, autotuned tiles, FP32 coarse-level smoothing inside the FP64 defect correction.  One
+step = one iteration of the batched solve driver: the FP64 fine-level residual check of every problem (with
+the divergence guard), then one FAS V-cycle (levels 5..1, beta 2/2/4).  value = fine-level DOF-residual
+evaluations per second over the timed steps (DOF x fine-level operator evaluations / wall time).
 
-One step = one isotropic FAS V-cycle (levels 6..1, beta_1 = beta_2 = 2 RK3 sweeps, 4 on the coarsest
-level) followed by the in-cycle anisotropic truncation-error estimate (3V cycle, isolated tau) on the
-same state: every stage of the hot path (residual, RK3 smoothing, restriction/prolongation, V-cycle,
-per-direction tau).  value = fine-level DOF-residual evaluations per second over the timed steps
-(DOF x fine-level residual evaluations contained in them / wall time).
+Secondary lines, each with its own roofline of the fine-level residual: the anisotropic O-grid around a
+sphere (4,992 curved hexes, orders iid {1..7}^3, 620,512 DOF; FP64 and mixed; step = a solve-driver
+iteration + the isolated 3V truncation-error estimate) and the flat plate (200,704 DOF; step = V-cycle +
+3V estimate).  roofline = the surveyed algorithmic bytes of one fine-level residual over its time measured
+with events on the launch stream; flops likewise from the surveyed flop model.
 """
 from __future__ import annotations
 
@@ -23,29 +27,280 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6    # MI355X FP64 vector (and matrix) peak
 KINDS = ["trace", "face1", "grad", "face2", "div", "dt", "transfer"]
 # the library's kernel kinds; "face2" is the numerical-flux pass (k_face2c on conforming and boundary faces,
-# k_face2 on p-nonconforming ones: the plate has only the former)
-KERNEL_NAME = {"trace": "k_trace", "face1": "k_face1", "grad": "k_grad", "face2": "k_face2c", "div": "k_div",
-               "dt": "k_dt", "transfer": "k_transfer"}
-PROFILE_STRIDE = 7  # the timed region brackets every 7th launch of the dominant kernel with events
+# k_face2 on p-nonconforming ones)
+KERNEL_NAME = {"trace": "k_trace", "face1": "k_face1", "grad": "k_grad", "face2": "k_face2c+k_face2",
+               "div": "k_div", "dt": "k_dt", "transfer": "k_transfer"}
+CPU_SHARE = 16  # host threads one GPU's share of the box allows
 
 
-def cpu_baseline(wl, evals: int):
-    """The oracle, as it is, on a bounded sample of the same workload: 'evals' fine-level residuals."""
+def alg_model(orders_list):
+    """(nodes, element face nodes, algorithmic bytes, flops) of one fine-level residual R(u), the surveyed
+    minimum: per node read Q (40 B) and the metric terms (80 B) and write R (40 B); per element face node its
+    traces of q and F^v . n (10 values) written by one side and read by the other (160 B); flops 34 sum_d n_d
+    + 650 per node and 125 per element face node (for isotropic order N: 102 (N+1) + 650 + 750 / (N+1) per
+    node, the gradient and divergence contractions, pointwise fluxes, lifts and face work)."""
     import numpy as np
+    nn = nf = fl = 0
+    for o in orders_list:
+        n = np.asarray(o, dtype=np.int64) + 1
+        npe = n.prod(axis=1)
+        fpe = 2 * (n[:, 1] * n[:, 2] + n[:, 0] * n[:, 2] + n[:, 0] * n[:, 1])
+        nn += int(npe.sum())
+        nf += int(fpe.sum())
+        fl += int((npe * (34 * n.sum(axis=1) + 650) + 125 * fpe).sum())
+    return nn, nf, 160.0 * (nn + nf), float(fl)
 
+
+_CPU_WORK = []  # (mesh, orders, phys, Q) of the sampled problems, shared with forked workers
+
+
+def _cpu_one(i):
     from oracle import oracle as O
-    o = O.Oracle(wl.mesh, wl.phys)
+    mesh, orders, phys, Q = _CPU_WORK[i]
+    R = O.Oracle(mesh, phys).residual(orders, Q)
+    return int(Q.shape[1]), bool(__import__("numpy").isfinite(R).all())
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(works, single_budget_s: float, pool_rounds: int) -> dict:
+    """The oracle, as it is, on a bounded sample of the same workload, before the GPU is touched: one thread
+    over the sampled problems' fine-level residuals until the budget is spent; then every host thread of the
+    GPU's share (at most 16), one process per thread, each evaluating whole problems' residuals (the batch's
+    problems are independent), over pool_rounds x threads problems."""
+    import multiprocessing as mp
+
+    _CPU_WORK[:] = works
     t0 = time.perf_counter()
-    for _ in range(evals):
-        R = o.residual(wl.orders, wl.Q)
-    dt = time.perf_counter() - t0
-    assert np.isfinite(R).all()
-    return {"value": wl.n_nodes * evals / dt, "unit": "DOF-residual evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{evals} fine-level residual evaluations R(u) of the same plate state (FP64 C oracle, "
-                      f"one thread, {dt:.1f} s)"}
+    dof = 0
+    n1 = 0
+    while n1 < len(works) and time.perf_counter() - t0 < single_budget_s:
+        d, ok = _cpu_one(n1)
+        assert ok
+        dof += d
+        n1 += 1
+    t1 = time.perf_counter() - t0
+    single = dof / t1
+    affinity = len(os.sched_getaffinity(0))
+    threads = max(1, min(CPU_SHARE, affinity))
+    idx = [i % len(works) for i in range(pool_rounds * threads)]
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS",)}
+    os.environ["OMP_NUM_THREADS"] = "1"
+    t2 = time.perf_counter()
+    with mp.get_context("fork").Pool(threads) as pool:
+        res = pool.map(_cpu_one, idx, chunksize=1)
+    t3 = time.perf_counter() - t2
+    for k, v in env.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+    assert all(ok for _, ok in res)
+    allc = sum(d for d, _ in res) / t3
+    return {"value": allc, "unit": "DOF-residual evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"fine-level residuals R(u) of whole problems of the same batch (FP64 C oracle): "
+                      f"{len(idx)} problem residuals on {threads} processes of one thread each in {t3:.1f} s; "
+                      f"one thread: {n1} problem residuals in {t1:.1f} s",
+            "single_thread": {"value": single, "cores": 1, "problems": n1, "seconds": t1},
+            "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity": affinity}}
+
+
+def residual_roofline(s, Q, orders_list, loops: int, counters_name: str):
+    """Fine-level R(u) back to back, timed with events on the stream the library launches on: its algorithmic
+    bytes and flops over that time (roofline), and each kernel's share (every launch bracketed by the
+    library's own events, in a separate shorter loop)."""
+    import torch
+
+    nn, nf, B, F = alg_model(orders_list)
+    R = s.empty()
+    for _ in range(3):
+        s.residual(Q, None, out=R)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(loops):
+        s.residual(Q, None, out=R)
+    e1.record(st)
+    e1.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / loops
+    s.profile(KINDS)
+    nk = max(3, loops // 10)
+    for _ in range(nk):
+        s.residual(Q, None, out=R)
+    torch.cuda.synchronize()
+    per = {k: s.profile_read(k) for k in KINDS}
+    s.profile([])
+    kern = {KERNEL_NAME[k]: {"us": round(1e3 * v[0] / nk, 2), "launches": v[1] // nk}
+            for k, v in per.items() if v[1]}
+    dominant = max(kern, key=lambda k: kern[k]["us"])
+    traffic, ratio = None, None
+    cpath = os.path.join(ROOT, "profiles", f"residual_{counters_name}_counters.json")
+    if os.path.exists(cpath):
+        from paper_1806_11456_amd import counters
+        with open(cpath) as f:
+            c = json.load(f)
+        if c.get("source_sha256") == counters.source_hash():
+            traffic = c["traffic_bytes_per_residual"]
+            ratio = traffic / B
+    achieved = B / t / 1e9
+    return {
+        "roofline": {"kernel": "fine-level residual R(u): " + ", ".join(kern), "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "traffic_over_alg": ratio, "alg_bytes_per_launch": B,
+                     "alg_bytes_model": "160 B per node + 160 B per element face node",
+                     "avg_launch_us": 1e6 * t, "nodes": nn, "element_face_nodes": nf,
+                     "dominant_kernel": dominant, "per_kernel_us": kern},
+        "flops": {"achieved_tflops": F / t / 1e12, "peak_tflops": FP64_PEAK_TFLOPS,
+                  "frac": F / t / 1e12 / FP64_PEAK_TFLOPS, "flops_per_residual": F},
+        "residual_only": {"value": nn / t, "unit": "DOF-residual evals/s", "us_per_residual": 1e6 * t},
+    }
+
+
+def timed(step, steps: int, warmup: int) -> float:
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def batch_line(args, wls) -> dict:
+    """Configuration of 64 independent problems: batched solve-driver iterations (mixed precision, graph
+    replay, autotuned tiles, divergence guard)."""
+    import numpy as np
+    import torch
+
+    from paper_1806_11456_amd import pmg
+
+    ctx = pmg.Context(0)
+    t0 = time.perf_counter()
+    meshes = [pmg.Mesh(ctx, w.mesh) for w in wls]
+    b1, b2, bc = args.beta
+    mg = pmg.MG(beta_pre=b1, beta_post=b2, beta_coarse=bc, precision=1, guard=8)
+    b = pmg.Batch(ctx, meshes, [w.orders for w in wls], [w.phys for w in wls], mg)
+    Q = b.tensor(np.concatenate([w.Q for w in wls], axis=1))
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    b.autotune()
+    b.set_graph(True)
+    roof = residual_roofline(b, Q, [w.orders for w in wls], args.residual_loops_batch, "batch64")
+    # one call per phase: each driver iteration is a residual check (+ guard) and a V-cycle; the call ends with
+    # one more check
+    b.solve_all(Q, None, tol=0.0, max_cycles=args.warmup, raise_not_converged=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cyc, r = b.solve_all(Q, None, tol=0.0, max_cycles=args.steps, raise_not_converged=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    halv, _ = b.guard_stats()
+    per_cycle = 3 * (b1 + b2) + 1
+    evals = args.steps * (per_cycle + 1) + 1
+    fp32 = b.fp32_cycles()
+    return {"value": b.n_nodes * evals / wall, "ms_per_step": 1e3 * wall / args.steps,
+            "config": {"workload": "64 independent steady problems (seed 4): random boxes of 2k..20k hexes "
+                                   "stretched toward a no-slip wall, orders iid U{2..5}^3, Mach U[0.1,0.4], "
+                                   "Re U[1e2,1e4], trilinear mapping, Gauss nodes",
+                       "dof": b.n_nodes, "problems": len(wls),
+                       "step": f"batched solve-driver iteration: FP64 residual check + divergence guard + one FAS "
+                               f"V-cycle (levels 5..1, beta {b1}/{b2}/{bc}), FP32 coarse levels, graph replay",
+                       "tiles": "autotuned per level", "fine_residual_evals_per_step": per_cycle + 1,
+                       "setup_s": round(setup, 2)},
+            "guard_halvings": int(halv.sum()), "problems_halved": int((halv > 0).sum()),
+            "fp32_cycles_min": int(fp32.min()), "residual_max": float(np.max(r)), **roof}
+
+
+def ogrid_line(args) -> dict:
+    """Anisotropic O-grid around a sphere, random orders 1..7: solve-driver iteration + isolated 3V tau."""
+    import torch
+
+    from paper_1806_11456_amd import inputs as I
+    from paper_1806_11456_amd import pmg
+
+    wl = I.config_ogrid()
+    ctx = pmg.Context(0)
+    mesh = pmg.Mesh(ctx, wl.mesh)
+    b1, b2, bc = args.beta
+    out = {}
+    for prec in (0, 1):
+        s = pmg.Solver(ctx, mesh, wl.orders, wl.phys, pmg.MG(beta_pre=b1, beta_post=b2, beta_coarse=bc,
+                                                              precision=prec, guard=8))
+        Q = s.tensor(wl.Q)
+        Qc = torch.empty_like(Q)
+        tau = s.tau_estimate(Q.clone(), None, isolated=True)  # builds every level
+        s.autotune()
+        s.set_graph(True)
+
+        def step():
+            s.solve(Q, None, tol=0.0, max_cycles=1, raise_not_converged=False)
+            Qc.copy_(Q)
+            s.tau_estimate(Qc, None, isolated=True, out=tau)
+
+        wall = timed(step, args.ogrid_steps, 1)
+        halv, _ = s.guard_stats()
+        if prec == 0:
+            per_cycle = 3 * (b1 + b2) + 1
+            evals = per_cycle + 2 + 3 * per_cycle  # cycle, two checks, one V-cycle per direction (3V)
+            out = {"value": s.n_nodes * evals * args.ogrid_steps / wall, "ms_per_step": 1e3 * wall / args.ogrid_steps,
+                   "config": {"workload": "O-grid around a unit sphere: 6 panels of 8x8 x 13 radial cells (4,992 "
+                                          "hexes, r in [1,20], ratio 1.25), quadratic mapping, rotated element "
+                                          "frames, orders iid U{1..7}^3 (seed 3), Mach 0.2, Re 200, Gauss nodes",
+                              "dof": s.n_nodes,
+                              "step": f"solve-driver iteration (residual checks + guard + FAS V-cycle, levels 7..1, "
+                                      f"beta {b1}/{b2}/{bc}) + isolated anisotropic 3V tau estimate of the state",
+                              "fine_residual_evals_per_step": evals},
+                   "guard_halvings": int(halv.sum()),
+                   **residual_roofline(s, Q, [wl.orders], args.residual_loops, "ogrid8x13")}
+        else:
+            out["mixed"] = {"ms_per_step": 1e3 * wall / args.ogrid_steps, "guard_halvings": int(halv.sum()),
+                            "speedup_vs_fp64": out["ms_per_step"] / (1e3 * wall / args.ogrid_steps)}
+        del s, Q, Qc
+    return out
+
+
+def plate_line(args) -> dict:
+    """Flat plate: isotropic V-cycle + isolated 3V tau estimate on the same state."""
+    from paper_1806_11456_amd import inputs as I
+    from paper_1806_11456_amd import pmg
+
+    wl = I.config_plate()
+    ctx = pmg.Context(0)
+    b1, b2, bc = args.beta
+    s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys, pmg.MG(beta_pre=b1, beta_post=b2, beta_coarse=bc))
+    Q = s.tensor(wl.Q)
+    s.tau_estimate(s.tensor(wl.Q), None, isolated=True)  # builds every level
+    s.autotune()
+
+    def step():
+        s.vcycle(Q, None, n_cycles=1)
+        s.tau_estimate(Q, None, isolated=True)
+
+    wall = timed(step, args.plate_steps, 2)
+    per_cycle = 3 * (b1 + b2) + 1
+    evals = per_cycle * 3  # the V-cycle and one cycle per direction with more than one level (x, y)
+    return {"value": s.n_nodes * evals * args.plate_steps / wall, "ms_per_step": 1e3 * wall / args.plate_steps,
+            "config": {"workload": "flat-plate boundary layer: 64x32x1 stretched hexes (ratio 1.1), quadratic "
+                                   "mapping, N=(6,6,1) Gauss, Mach 0.2, Re_L 1e5, wall + far field",
+                       "dof": s.n_nodes,
+                       "step": f"isotropic FAS V-cycle (levels 6..1, beta {b1}/{b2}/{bc}) + anisotropic 3V "
+                               f"isolated tau", "fine_residual_evals_per_step": evals},
+            **residual_roofline(s, Q, [wl.orders], args.residual_loops, "plate64x32")}
 
 
 def serve_bench(args) -> dict:
@@ -432,7 +687,7 @@ def sphere_multistage_bench(args) -> dict:
     K = mesh_h.K
     out = {}
     cases = (("single-stage", 6, (6,)), ("multi-stage", 4, (4, 6)))
-    for label, first, stages in [c for c in cases if args.sphere_only in ("", c[0])]:
+    for label, first, stages in cases:
         print(f"sphere-multistage {label}: start", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -440,7 +695,7 @@ def sphere_multistage_bench(args) -> dict:
         # the final solve continues here in chunks, with progress lines, on a solver like the driver's
         N, Q, reps, _, _ = pmg.adapt_multistage(
             ctx, mesh, I.uniform_orders(K, (first,) * 3), phys, mg, stages, args.sphere_tau_max,
-            (args.sphere_nmax,) * 3, 4, 2,
+            (6, 6, 6), 4, 2,
             True, conv=0.1, final_tol=1e30, max_cycles=args.sphere_max_cycles, raise_not_converged=False,
             n_coarse=2)
         torch.cuda.synchronize()
@@ -450,17 +705,6 @@ def sphere_multistage_bench(args) -> dict:
         s = pmg.Solver(ctx, mesh, N, phys, pmg.MG(level_caps=list(range(top, 1, -1)), beta_pre=2, beta_post=2,
                                                 beta_coarse=4))
         Q = Q.clone()
-        if args.sphere_probe_smooth:
-            # RK3 alone on the adapted fine level (a copy): separates the fine discretisation from the cycle
-            Qs = Q.clone()
-            for k in range(args.sphere_probe_smooth):
-                s.smooth(Qs, None, sweeps=200)
-                rs = s.residual(Qs, None, norm=True)[1]
-                print(f"sphere-multistage {label}: RK3 only, {200 * (k + 1)} sweeps, residual {rs:.3e}",
-                      file=sys.stderr, flush=True)
-                if rs != rs:
-                    break
-            del Qs
         cyc, res = 0, s.residual(Q, None, norm=True)[1]
         while res > args.sphere_tol and cyc < args.sphere_max_cycles and res == res:
             res = s.vcycle(Q, None, n_cycles=args.sphere_chunk, norm=True)
@@ -488,7 +732,7 @@ def sphere_multistage_bench(args) -> dict:
                 "speed-up of the multi-stage run over the single-stage run (wall time of the driver calls)",
             "n_gpus": 1, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "sphere, Re_D 200, Mach 0.2, six-panel O-grid 8x8x13 per panel (4992 hexes)",
-                       "tau_max": args.sphere_tau_max, "tol": args.sphere_tol, "n_max": args.sphere_nmax, "n_min": 4,
+                       "tau_max": args.sphere_tau_max, "tol": args.sphere_tol, "n_max": 6, "n_min": 4,
                        "jump_rule": "floor(2N/3)", "wall_conforming": True, "levels": "max .. 2",
                        "mg": "beta 2/2/4, FMG start (threshold 1.0)"},
             "order6_reference_cd": ref, "runs": out}
@@ -497,14 +741,18 @@ def sphere_multistage_bench(args) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--beta", type=int, nargs=3, default=[2, 2, 4], metavar=("PRE", "POST", "COARSE"))
     ap.add_argument("--residual-loops", type=int, default=200)
-    ap.add_argument("--cpu-evals", type=int, default=15)  # about 13 s of one CPU thread
+    ap.add_argument("--residual-loops-batch", type=int, default=20)
+    ap.add_argument("--ogrid-steps", type=int, default=10)
+    ap.add_argument("--plate-steps", type=int, default=20)
+    ap.add_argument("--lines", default="batch,ogrid,plate",
+                    help="workloads, the first one is the headline: batch, ogrid, plate")
+    ap.add_argument("--cpu-single-s", type=float, default=12.0)
+    ap.add_argument("--cpu-rounds", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="first run one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--serve", action="store_true", help="served-stream latency benchmark instead of the plate")
     ap.add_argument("--serve-n", type=int, default=24)
     ap.add_argument("--serve-kmin", type=int, default=64)
@@ -532,9 +780,6 @@ def main() -> int:
     ap.add_argument("--sphere-multistage", action="store_true", help="multi-stage vs single-stage adaptation")
     ap.add_argument("--sphere-tau-max", type=float, default=2.761e-2)
     ap.add_argument("--sphere-max-cycles", type=int, default=40000)
-    ap.add_argument("--sphere-nmax", type=int, default=6)
-    ap.add_argument("--sphere-only", default="", choices=["", "single-stage", "multi-stage"])
-    ap.add_argument("--sphere-probe-smooth", type=int, default=0, help="chunks of 200 RK3 sweeps before the final solve")
     ap.add_argument("--compare-s", type=float, default=40.0)
     ap.add_argument("--compare-rk-chunk", type=int, default=1000)
     ap.add_argument("--compare-fas-chunk", type=int, default=20)
@@ -566,138 +811,57 @@ def main() -> int:
         print(json.dumps(sphere_multistage_bench(args)), flush=True)
         return 0
 
-    import numpy as np
+    from paper_1806_11456_amd import inputs as I
+
+    lines = [x for x in args.lines.split(",") if x]
+    assert lines and all(x in ("batch", "ogrid", "plate") for x in lines), args.lines
+    head = lines[0]
+    wls = I.config_batch() if "batch" in lines else None
+    cpu = None
+    if not args.no_cpu and head == "batch":
+        # before the GPU is touched: forked oracle workers
+        cpu = cpu_baseline([(w.mesh, w.orders, w.phys, w.Q) for w in wls], args.cpu_single_s, args.cpu_rounds)
+    elif not args.no_cpu:
+        wl = I.config_ogrid() if head == "ogrid" else I.config_plate()
+        cpu = cpu_baseline([(wl.mesh, wl.orders, wl.phys, wl.Q)], args.cpu_single_s, args.cpu_rounds)
+
     import torch
 
-    from paper_1806_11456_amd import inputs as I
-    from paper_1806_11456_amd import pmg
-
-    if args.copy_mib:
-        src = torch.ones(args.copy_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    wl = I.config_plate()
-    ctx = pmg.Context(0)
-    b1, b2, bc = args.beta
-    s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys, pmg.MG(beta_pre=b1, beta_post=b2, beta_coarse=bc))
-    dof = s.n_nodes
-    Q = s.tensor(wl.Q)
-
-    def step():
-        s.vcycle(Q, None, n_cycles=1)
-        s.tau_estimate(Q, None, isolated=True)
-
-    # fine-level residual evaluations per step: each V-cycle on its top level runs 3 (beta_1 + beta_2) RK
-    # stages plus the residual it restricts; tau runs one such cycle per direction with more than one level
-    per_cycle = 3 * (b1 + b2) + 1
-    tau_dirs = sum(1 for d in range(3) if int(wl.orders[:, d].max()) > 1)
-    evals_per_step = per_cycle * (1 + tau_dirs)
-
-    # one step builds every level (the anisotropic hierarchies on first use); the tile autotuner then picks
-    # each level's element-tile size
-    step()
-    torch.cuda.synchronize()
-    s.autotune()
-    # warm-up; the first step times every kernel kind to find the dominant one
-    s.profile(KINDS)
-    step()
-    torch.cuda.synchronize()
-    per_kind = {k: s.profile_read(k) for k in KINDS}
-    dominant = max(KINDS, key=lambda k: per_kind[k][0])
-    s.profile([])
-    for _ in range(max(args.warmup - 1, 0)):
-        step()
-    torch.cuda.synchronize()
-
-    # timed region: the dominant kernel's launches are bracketed by events on their stream, every
-    # PROFILE_STRIDE-th launch (a prime: every launch position of the step is sampled over the run)
-    s.profile([dominant], stride=PROFILE_STRIDE)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k_ms, k_n, k_bytes = s.profile_read(dominant)
-    s.profile([])
-    if not torch.isfinite(Q).all():
-        print("non-finite state after the timed steps", file=sys.stderr)
-        return 1
-    wall = t1 - t0
-    value = dof * evals_per_step * args.steps / wall
-    achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
-
-    # residual-only rate (fine-level R(u) back to back) for comparison with the CPU oracle
-    R = s.empty()
-    for _ in range(10):
-        s.residual(Q, None, out=R)
-    torch.cuda.synchronize()
-    r0 = time.perf_counter()
-    for _ in range(args.residual_loops):
-        s.residual(Q, None, out=R)
-    torch.cuda.synchronize()
-    r_wall = time.perf_counter() - r0
-
-    # HBM traffic of the dominant kernel from the committed counter summary (rocprofv3 FETCH_SIZE/WRITE_SIZE
-    # on the plate's V-cycles and residuals), while the sources still hash to the recorded value: the measured
-    # traffic / compulsory-bytes ratio of those launches applied to this run's compulsory bytes per launch
-    traffic, traffic_measured = None, None
-    cpath = os.path.join(ROOT, "profiles", f"{KERNEL_NAME[dominant]}_plate64x32_N661_counters.json")
-    if os.path.exists(cpath):
-        from paper_1806_11456_amd import counters
-        with open(cpath) as f:
-            c = json.load(f)
-        if c.get("source_sha256") == counters.source_hash() and "traffic_over_alg" in c:
-            traffic = c["traffic_over_alg"] * (k_bytes / max(k_n, 1))
-            traffic_measured = {"bytes_per_launch": c["traffic_bytes_per_launch"],
-                                "alg_bytes_per_launch": c["alg_bytes_per_launch"],
-                                "ratio": c["traffic_over_alg"], "dispatches": c["dispatches"],
-                                "workload": "plate V-cycles + residuals (profile_plate)"}
-
+    results = {}
+    for name in lines:
+        fn = {"batch": lambda: batch_line(args, wls), "ogrid": lambda: ogrid_line(args), "plate": lambda: plate_line(args)}
+        results[name] = fn[name]()
+        print(f"{name}: {results[name]['value']:.4g} DOF-residual evals/s, {results[name]['ms_per_step']:.2f} ms/step, "
+              f"roofline frac {results[name]['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    h = results[head]
+    dtype = {"batch": "f64/f32 (FP64 finest level and checks, FP32 coarse-level smoothing)", "ogrid": "f64",
+             "plate": "f64"}[head]
+    steps = args.steps if head == "batch" else (args.ogrid_steps if head == "ogrid" else args.plate_steps)
     out = {
         "metric": "fine-level DOF-residual evals/s",
-        "value": value,
+        "value": h["value"],
         "unit": "DOF-residual evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "steps": steps,
+        "warmup": args.warmup if head == "batch" else (1 if head == "ogrid" else 2),
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {
-            "workload": "flat-plate boundary layer: 64x32x1 stretched hexes (ratio 1.1), quadratic mapping, "
-                        "N=(6,6,1) Gauss, Mach 0.2, Re_L 1e5, wall + far field",
-            "dof": dof,
-            "step": f"isotropic FAS V-cycle (levels 6..1, beta {b1}/{b2}/{bc}) + anisotropic 3V isolated tau",
-            "tiles": "autotuned per level",
-            "fine_residual_evals_per_step": evals_per_step,
-        },
-        "roofline": {
-            "kernel": KERNEL_NAME[dominant],
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "traffic_measured": traffic_measured,
-            "avg_launch_us": 1e3 * k_ms / max(k_n, 1),
-            "launches": k_n,
-            "timed_every": PROFILE_STRIDE,
-            "alg_bytes_per_launch": k_bytes / max(k_n, 1),
-        },
-        "residual_only": {"value": dof * args.residual_loops / r_wall, "unit": "DOF-residual evals/s",
-                          "us_per_residual": 1e6 * r_wall / args.residual_loops},
-        "kernel_ms_first_step": {KERNEL_NAME[k]: round(v[0], 3) for k, v in per_kind.items()},
+        "config": h["config"],
+        "roofline": h["roofline"],
+        "flops": h["flops"],
+        "residual_only": h["residual_only"],
+        "lines": {k: v for k, v in results.items() if k != head},
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_evals)
+    for k in ("guard_halvings", "problems_halved", "fp32_cycles_min", "residual_max", "mixed"):
+        if k in h:
+            out[k] = h[k]
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 

@@ -98,6 +98,11 @@ typedef struct {
                                 floor of the FP32 correction), so the converged solution is an FP64 solution. */
   int32_t mixed_patience;    /* precision 1: cycles without a new minimum of the residual before the switch
                                 (0 = 4) */
+  int32_t guard;             /* divergence guard of pmg_solve / pmg_batch_solve: 0 off; n > 0: a problem whose
+                                residual check is non-finite or grew more than 1e4-fold over one cycle gets
+                                back its state of the previous check and both explicit step constants halved,
+                                at most n times (then PMG_ERR_NONPHYSICAL as without the guard).  The halved
+                                constants stay with the solver (pmg_guard_stats). */
 } pmg_mg_params;
 
 const char* pmg_last_error(void);
@@ -287,6 +292,13 @@ pmg_status pmg_server_poll(pmg_server sv, uint64_t ticket, int* done, int* statu
 pmg_status pmg_server_stats(pmg_server sv, int* resident, int* queued, int64_t* completed, int64_t* iterations,
                             int64_t* bytes_in_use, int64_t* peak_bytes, int* max_resident);
 void pmg_server_destroy(pmg_server sv);
+
+/*
+ * Per problem: the step-constant halvings the divergence guard (pmg_mg_params.guard) made since the solver
+ * was created (halvings[n_problems], host, out) and, if cfl_host is not NULL, the current constants
+ * (cfl_host[2 n_problems]: C^a, C^nu of each problem; the step limits of Sec. 2).
+ */
+pmg_status pmg_guard_stats(pmg_solver s, int32_t* halvings, double* cfl_host);
 
 /* Mixed precision (pmg_mg_params.precision = 1, Sec. 3.1 cycle with FP32 coarse levels): fp32_cycles (host,
  * one entry per problem) receives the number of cycles of the last pmg_solve / pmg_batch_solve that ran

@@ -315,6 +315,8 @@ struct pmg_solver_s {
   int* d_act[2] = {nullptr, nullptr};        // per problem: the problems a batched cycle advances
   std::unique_ptr<Hier> iso64;               // FP64 isotropic hierarchy of a mixed-precision solver
   std::vector<int> fp32_cycles;              // per problem: cycles of the last solve with FP32 coarse levels
+  std::vector<int> halvings;                 // per problem: step-constant halvings by the divergence guard
+  double* d_Qbak = nullptr;                  // [5][nn] the state at the last accepted check (divergence guard)
   // the shared face-trace array holds the traces of this state on this level (launch-order bookkeeping:
   // k_trace is skipped when the next evaluation is of the same state on the same level)
   mutable const Level* qf_level = nullptr;
@@ -825,7 +827,8 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
                   k_face2c<T><<<L.nfctiles, PMG_FACE_TILE, 0, st>>>(D, L.d_fcrec, W.qf, W.fvn, W.Phi));
     if (L.nf1tiles > 0)
       PROF_LAUNCH(s, PK_FACE2, st, (17 * ncf + 4 * (nm - cm) + 5 * ncf) * w,
-                  k_face2<T><<<L.nf1tiles, PMG_FACE_TILE, 0, st>>>(D, L.d_f1list, W.qf, W.gf, W.Phi));
+                  k_face2<T><<<L.nf1tiles, PMG_FACE_TILE, 34 * PMG_FACE_TILE * sizeof(T), st>>>(D, L.d_f1list, W.qf,
+                                                                                           W.gf, W.Phi));
   }
   // divergence: Q, grad W, J a, 1/J, Phi in; the epilogue's own arrays
   double epi = 0.0;
@@ -1477,6 +1480,8 @@ static pmg_solver_s* create_solver(pmg_ctx ctx, const std::vector<const pmg_mesh
   s->mg.level_caps = nullptr;
   s->iso_caps = caps;
   s->fp32_cycles.assign(n, 0);
+  s->halvings.assign(n, 0);
+  REQUIRE(s->mg.guard >= 0, "negative guard");
   build_hier(s.get(), s->iso, -1, caps, s->mg.precision == 1 ? PREC_F32 : PREC_F64);
   size_t nq = 5 * (size_t)s->top->nn;
   s->d_zero = s->arena.alloc<double>(nq);
@@ -1584,6 +1589,7 @@ static double solver_footprint(const pmg_mesh_s* m, const int32_t* orders, const
     }
   }
   b += sizeof(Phys) + 4.0 * K + 3 * 4.0 + 8.0 * NSLOTS + 8.0 * K + 3 * 5 * 8.0 * nn_top;  // solver arrays
+  if (mg && mg->guard > 0) b += 5 * 8.0 * nn_top;  // the divergence guard's state copy (first guarded solve)
   if (transient) *transient = 12.0 * 8.0 * nn_top;
   if (switch_extra) *switch_extra = extra;
   return b;
@@ -1875,18 +1881,63 @@ static void cycle_once(pmg_solver_s* s, Hier& H, int kind, double* Q, const doub
 
 // Stopping and precision bookkeeping of one problem: FP32 coarse levels are kept while the residual keeps
 // reaching new minima; after 'patience' cycles without one (the FP32 round-off floor of the coarse
-// correction) the problem continues with FP64 coarse levels.
+// correction) the problem continues with FP64 coarse levels.  Cycles count as stalled only once the residual
+// has fallen below its first value: a start-up transient that raises the residual is no round-off floor.
 struct MixedState {
   int f32 = 0, stall = 0;
-  double best = INFINITY;
+  double best = INFINITY, first = -1.0;
   void update(double r, int patience) {
     if (!f32) return;
+    if (first < 0.0) first = r;
     if (r < best) {
       best = r;
       stall = 0;
-    } else if (++stall >= patience) {
+    } else if (best < first && ++stall >= patience) {
       f32 = 0;
     }
+  }
+};
+
+// Divergence guard of the solve drivers (mg.guard > 0).  At every residual check, a problem whose residual is
+// no longer finite, or grew more than 1e4-fold over the last cycle, gets back its state of the previous check
+// and continues with both explicit step constants halved (at most mg.guard times; then the solve fails as
+// without the guard).  The halved constants stay with the solver.  The state of every problem is copied at
+// each accepted check (one device copy of the finest state; a V-cycle costs far more).
+struct DivGuard {
+  pmg_solver_s* s;
+  hipStream_t st;
+  std::vector<double> r_ok;  // residual at the last accepted check
+  bool first = true;
+  DivGuard(pmg_solver_s* s_, hipStream_t st_) : s(s_), st(st_), r_ok(s_->nprob, 0.0) {
+    if (s->mg.guard > 0 && !s->d_Qbak) s->d_Qbak = s->arena.alloc<double>(5 * (size_t)s->top->nn);
+  }
+  // r: this check's residuals (restored problems get their previous residual back); advanced: the problems the
+  // last cycle moved.  Returns false when a problem has used up its halvings (the caller fails as unguarded).
+  bool check(std::vector<double>& r, const std::vector<int>& advanced, double* Q) {
+    if (s->mg.guard <= 0) return true;
+    const Level& T = *s->top;
+    bool restored = false;
+    for (int p = 0; p < s->nprob && !first; p++) {
+      if (!advanced[p]) continue;
+      if (r[p] == r[p] && !(r[p] > 1e4 * r_ok[p])) continue;
+      if (s->halvings[p] >= s->mg.guard) return false;
+      s->halvings[p]++;
+      const size_t n0 = T.off[s->prob_elem[p]], n1 = T.off[s->prob_elem[p + 1]];
+      for (int v = 0; v < 5; v++)
+        HIPCHECK(hipMemcpyAsync(Q + (size_t)v * T.nn + n0, s->d_Qbak + (size_t)v * T.nn + n0,
+                                (n1 - n0) * sizeof(double), hipMemcpyDeviceToDevice, st));
+      s->phys[p].cfl_adv *= 0.5;
+      s->phys[p].cfl_visc *= 0.5;
+      HIPCHECK(hipStreamSynchronize(st));
+      HIPCHECK(hipMemcpy(s->d_ptab + p, &s->phys[p], sizeof(Phys), hipMemcpyHostToDevice));
+      r[p] = r_ok[p];
+      restored = true;
+    }
+    if (restored) traces_stale(s);
+    for (int p = 0; p < s->nprob; p++) r_ok[p] = r[p];
+    first = false;
+    copy(s->d_Qbak, (const double*)Q, 5 * (size_t)T.nn, st);
+    return true;
   }
 };
 
@@ -1926,9 +1977,14 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
     MixedState ms;
     ms.f32 = mixed;
     s->history.clear();
+    DivGuard dg(s, st);
+    const std::vector<int> one(1, 1);
     for (;;) {
       residual(s, *s->top, (const double*)Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
       r = read_slot(s, SLOT_NORM, st);
+      std::vector<double> rv(1, r);
+      if (!dg.check(rv, one, Q_dev)) throw PmgError(PMG_ERR_NONPHYSICAL, "diverged after every step halving");
+      r = rv[0];
       s->history.push_back(r);
       if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
       if (r < tol || cycles >= max_cycles) break;
@@ -1966,9 +2022,12 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
     std::vector<MixedState> ms(n);
     for (auto& m : ms) m.f32 = mixed;
     std::vector<double> r(n, 0.0);
+    DivGuard dg(s, st);
     for (;;) {
       residual(s, *s->top, (const double*)Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);  // every problem
       r = read_slots(s, SLOT_NORM, st);
+      if (!dg.check(r, active, Q_dev))
+        throw PmgError(PMG_ERR_NONPHYSICAL, "a problem diverged after every step halving");
       int n32 = 0, n64 = 0;
       for (int p = 0; p < n; p++) {
         if (r[p] != r[p]) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual in problem " + std::to_string(p));
@@ -2004,6 +2063,19 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
     if (!all) throw PmgError(PMG_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance in some problem");
   });
   return rc;
+}
+
+pmg_status pmg_guard_stats(pmg_solver s, int32_t* halvings, double* cfl_host) {
+  return guard([&] {
+    REQUIRE(s && halvings, "NULL argument");
+    for (int p = 0; p < s->nprob; p++) {
+      halvings[p] = s->halvings[p];
+      if (cfl_host) {
+        cfl_host[2 * p] = s->phys[p].cfl_adv;
+        cfl_host[2 * p + 1] = s->phys[p].cfl_visc;
+      }
+    }
+  });
 }
 
 pmg_status pmg_solve_stats(pmg_solver s, int32_t* fp32_cycles) {
@@ -2224,6 +2296,7 @@ pmg_status pmg_server_submit(pmg_server sv, pmg_mesh mesh, const int32_t* orders
     REQUIRE(mesh->ctx == sv->ctx, "mesh belongs to another context");
     REQUIRE(max_cycles >= 0, "negative max_cycles");
     REQUIRE(!mg || (!mg->tuning && !mg->fmg), "served solves use fixed sweep counts and no FMG start");
+    REQUIRE(!mg || mg->guard == 0, "the divergence guard belongs to pmg_solve / pmg_batch_solve, not to served solves");
     for (int64_t i = 0; i < 3 * mesh->K; i++) REQUIRE(orders[i] >= 1 && orders[i] <= PMG_MAXN - 1, "orders must be 1..7");
     auto r = std::make_shared<ServerReq>();
     r->mesh = mesh;

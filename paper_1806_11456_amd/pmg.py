@@ -27,7 +27,7 @@ EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_crea
            "pmg_remap_state", "pmg_adapt_multistage", "pmg_wall_force", "pmg_wall_force_noalloc",
            "pmg_force_coefficients", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
-           "pmg_level_tiles", "pmg_solve_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
+           "pmg_level_tiles", "pmg_solve_stats", "pmg_guard_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
            "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy", "pmg_tau_nodal",
            "pmg_solve_history", "pmg_cycle_count", "pmg_checkpoint", "pmg_restore"]
 
@@ -51,7 +51,7 @@ class MGParams(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("level_caps", C.POINTER(C.c_int32)), ("beta_pre", C.c_int32),
                 ("beta_post", C.c_int32), ("beta_coarse", C.c_int32), ("tuning", C.c_int32), ("eta", C.c_double),
                 ("max_repeats", C.c_int32), ("fmg", C.c_int32), ("fmg_threshold", C.c_double),
-                ("precision", C.c_int32), ("mixed_patience", C.c_int32)]
+                ("precision", C.c_int32), ("mixed_patience", C.c_int32), ("guard", C.c_int32)]
 
 
 @dataclasses.dataclass
@@ -67,6 +67,7 @@ class MG:
     fmg_threshold: float = 0.1
     precision: int = 0  # 0 all FP64; 1 mixed (FP32 coarse-level smoothing, FP64 finest level)
     mixed_patience: int = 0  # mixed: cycles without a new residual minimum before FP64 coarse levels (0 = 4)
+    guard: int = 0  # divergence guard of the solve drivers: at most this many halvings of the step constants
 
 
 _lib = None
@@ -130,6 +131,7 @@ def lib():
     L.pmg_autotune.argtypes = [P, V]
     L.pmg_level_tiles.argtypes = [P, C.c_int, C.c_int, I32]
     L.pmg_solve_stats.argtypes = [P, I32]
+    L.pmg_guard_stats.argtypes = [P, I32, D]
     L.pmg_footprint.argtypes = [P, I32, C.POINTER(MGParams), I64, I64, I64]
     L.pmg_device_bytes.argtypes = [I64]
     L.pmg_server_create.argtypes = [P, C.c_int64, C.c_int, C.c_int, pp]
@@ -206,7 +208,7 @@ def mg_struct(mg):
     p = MGParams(0 if caps is None else len(caps),
                  None if caps is None else caps.ctypes.data_as(C.POINTER(C.c_int32)),
                  mg.beta_pre, mg.beta_post, mg.beta_coarse, mg.tuning, mg.eta, mg.max_repeats, mg.fmg,
-                 mg.fmg_threshold, mg.precision, mg.mixed_patience)
+                 mg.fmg_threshold, mg.precision, mg.mixed_patience, mg.guard)
     return p, caps
 
 
@@ -449,6 +451,15 @@ class Solver:
         _check(lib().pmg_solve_stats(self.h, out.ctypes.data_as(C.POINTER(C.c_int32))))
         return out
 
+    def guard_stats(self):
+        """Per problem: (step-constant halvings of the divergence guard, current (C^a, C^nu))."""
+        n = getattr(self, "n", 1)
+        h = np.zeros(n, dtype=np.int32)
+        c = np.zeros((n, 2))
+        _check(lib().pmg_guard_stats(self.h, h.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     c.ctypes.data_as(C.POINTER(C.c_double))))
+        return h, c
+
     def profile(self, kinds, stride: int = 1):
         """Bracket every stride-th launch of the given kernel kinds with HIP events (empty = off)."""
         mask = 0
@@ -465,9 +476,9 @@ class Solver:
         _check(lib().pmg_profile_read(self.h, KINDS[kind], C.byref(ms), C.byref(n), C.byref(b)))
         return ms.value, int(n.value), b.value
 
-    def tau_estimate(self, Q, S=None, isolated=True):
+    def tau_estimate(self, Q, S=None, isolated=True, out=None):
         nt = max(self.nmax - 1, 1)
-        tau = self.torch.empty((self.K, 3, nt), dtype=self.torch.float64, device=self.device)
+        tau = self.torch.empty((self.K, 3, nt), dtype=self.torch.float64, device=self.device) if out is None else out
         _check(lib().pmg_tau_estimate(self.h, _ptr(Q), _ptr(S), int(bool(isolated)), _ptr(tau), _stream()))
         return tau
 

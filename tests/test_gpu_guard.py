@@ -1,0 +1,64 @@
+"""Divergence guard of the solve drivers on the GPU.
+
+One problem of a batch is given explicit step constants far beyond the stability limit of its smoother.
+Without the guard the batched solve stops with a non-finite residual; with it that problem gets back its
+previous state with halved constants until it stays finite, the others are untouched (bitwise their own
+solves), and the guarded problem's batched result equals its own guarded solve bitwise.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1806_11456_amd import inputs as I
+from tests.gpu_util import np_
+
+pytestmark = pytest.mark.gpu
+
+MG = dict(beta_pre=2, beta_post=1, beta_coarse=3)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1806_11456_amd import pmg
+    assert torch.cuda.is_available()
+    return pmg.Context(0)
+
+
+def _problems():
+    probs = I.config_batch(n=3, kmin=20, kmax=60, seed=7)
+    bad = probs[1]
+    probs[1] = dataclasses.replace(bad, phys=dataclasses.replace(bad.phys, cfl_adv=40.0, cfl_visc=40.0))
+    return probs
+
+
+def test_guard_restores_and_halves(ctx):
+    from paper_1806_11456_amd import pmg
+    probs = _problems()
+    meshes = [pmg.Mesh(ctx, w.mesh) for w in probs]
+
+    def batch(guard):
+        b = pmg.Batch(ctx, meshes, [w.orders for w in probs], [w.phys for w in probs], pmg.MG(guard=guard, **MG))
+        return b, b.tensor(np.concatenate([w.Q for w in probs], axis=1))
+
+    b0, Q0 = batch(0)
+    with pytest.raises(pmg.PmgError, match="NONPHYSICAL"):
+        b0.solve_all(Q0, None, tol=1e-30, max_cycles=12, raise_not_converged=False)
+
+    b, Q = batch(10)
+    cyc, r = b.solve_all(Q, None, tol=1e-30, max_cycles=12, raise_not_converged=False)
+    h, cfl = b.guard_stats()
+    print(f"[guard] halvings {h.tolist()}, constants {cfl.tolist()}, cycles {list(cyc)}, residuals {list(r)}")
+    assert h[0] == 0 and h[2] == 0 and 1 <= h[1] <= 10
+    assert np.allclose(cfl[1], 40.0 / 2.0 ** h[1], rtol=0, atol=0)
+    assert np.isfinite(np_(Q)).all() and np.isfinite(r).all()
+    assert list(cyc) == [12, 12, 12]
+    for p, (m, w) in enumerate(zip(meshes, probs)):
+        s = pmg.Solver(ctx, m, w.orders, w.phys, pmg.MG(guard=10, **MG))
+        Qs = s.tensor(w.Q)
+        cs, rs = s.solve(Qs, None, tol=1e-30, max_cycles=12, raise_not_converged=False)
+        hs, _ = s.guard_stats()
+        assert hs[0] == h[p], (p, hs, h)
+        assert cs == cyc[p] and rs == r[p], (p, cs, rs, cyc[p], r[p])
+        assert np.array_equal(np_(b.part(Q, p)), np_(Qs)), p

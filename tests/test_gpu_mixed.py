@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from paper_1806_11456_amd import inputs as I
-from tests.gpu_util import check, np_
+from tests.gpu_util import check, np_, state_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -66,13 +66,14 @@ def test_mixed_vcycle_tracks_fp64_oracle(ctx, problem):
     Qm, Qd = mixed.tensor(Q0), fp64.tensor(Q0)
     mixed.vcycle(Qm, mixed.tensor(S), n_cycles=1)
     fp64.vcycle(Qd, fp64.tensor(S), n_cycles=1)
+    o.take_eval_count()
     Qo, _ = o.vcycles(orders, Q0, S, ncycles=1, **MG)  # default levels: max order down to 1, as the solver's
-    # the coarse levels hold the state rounded to FP32 and each RK stage there rounds again: the correction
-    # carries a few FP32 units (2^-24 max |Q_v|) of noise per stage; bound: 100 units
-    u32 = 2.0 ** -24
-    scale = np.abs(Q0).max(axis=1, keepdims=True)
-    err = check(np_(Qm) - Q0, Qo - Q0, scale, 100 * u32, "mixed V-cycle correction")
-    print(f"mixed V-cycle correction error: {err / u32:.1f} FP32 units of max |Q|")
+    # the FP64 state bar (n dt s_v for the oracle's n evaluations, at 1e-12) with the FP32 unit in place of the
+    # FP64 one: the coarse levels round the state and every operator term in FP32
+    ss, _ = state_scale(o, I.Workload("m", mesh, orders, ph, Q0), o.take_eval_count())
+    tol32 = 1e-12 * 2.0 ** 29
+    err = check(np_(Qm) - Q0, Qo - Q0, ss, tol32, "mixed V-cycle correction")
+    print(f"mixed V-cycle correction error: {err / 2.0 ** -24:.3g} FP32 units of the state scale")
     assert not np.array_equal(np_(Qm), np_(Qd)), "mixed cycle is bitwise the FP64 cycle: FP32 levels not used"
 
 
