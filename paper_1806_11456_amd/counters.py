@@ -1,4 +1,8 @@
-"""HBM traffic per launch of one kernel from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE).
+"""HBM traffic from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE), and kernel statistics.
+
+Per launch of one kernel (--kernel), or per fine-level residual of profile_residual.py (--residual R: the
+dispatches of the last R residuals, delimited by the divergence kernel that ends each of them); the
+statistics mode (--stats DIR) prints a per-kernel table of a --kernel-trace run.
 
 Each counter is scaled by what it reads for a plain device copy of known size run in the same process (the
 largest copy dispatch): a copy of B bytes reads B and writes B.  The result is written as JSON (read by
@@ -57,18 +61,109 @@ def _per_kernel(rows, kernel):
     return sum(vals) / len(vals), len(vals), max(copies)[1]
 
 
+RESIDUAL_KERNELS = ("k_trace", "k_face1", "k_grad", "k_face2c", "k_face2", "k_div")
+
+
+def _base(name: str) -> str:
+    return name.split("(")[0].split("<")[0].replace("void ", "").strip()
+
+
+def _last_residuals(rows, R):
+    """Rows of the dispatches of the last R fine-level residuals (each ends with one k_div dispatch)."""
+    key = (lambda r: int(r["Dispatch_Id"])) if rows and "Dispatch_Id" in rows[0] else None
+    order = sorted(range(len(rows)), key=(lambda i: key(rows[i])) if key else (lambda i: i))
+    divs = [i for i in order if _base(rows[i]["Kernel_Name"]) == "k_div"]
+    if len(divs) < R + 1:
+        raise SystemExit(f"fewer than {R + 1} k_div dispatches")
+    start = order.index(divs[-R - 1]) + 1
+    return [rows[i] for i in order[start:] if _base(rows[i]["Kernel_Name"]) in RESIDUAL_KERNELS]
+
+
+def residual_traffic(fetch_dir, write_dir, R, copy_mib, out_path, command, alg_bytes):
+    fr, wr = _rows(fetch_dir), _rows(write_dir)
+    f_copy = max((int(r["Grid_Size"]), float(r["Counter_Value"])) for r in fr if "copyBuffer" in r["Kernel_Name"])[1]
+    w_copy = max((int(r["Grid_Size"]), float(r["Counter_Value"])) for r in wr if "copyBuffer" in r["Kernel_Name"])[1]
+    copy_kib = copy_mib * 1024.0
+    fs, ws = copy_kib / f_copy, copy_kib / w_copy
+    per = {}
+    for rows, scale, col in ((_last_residuals(fr, R), fs, "fetch"), (_last_residuals(wr, R), ws, "write")):
+        for r in rows:
+            k = _base(r["Kernel_Name"])
+            per.setdefault(k, {"fetch": 0.0, "write": 0.0})
+            per[k][col] += float(r["Counter_Value"]) * scale * 1024.0 / R
+    total = sum(v["fetch"] + v["write"] for v in per.values())
+    out = {"residuals": R, "traffic_bytes_per_residual": total, "per_kernel_bytes": per, "fetch_scale": fs,
+           "write_scale": ws, "alg_bytes_per_residual": alg_bytes, "traffic_over_alg": total / alg_bytes,
+           "source_sha256": source_hash(), "command": command}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    md = os.path.splitext(out_path)[0] + ".md"
+    with open(md, "w") as f:
+        f.write("# HBM traffic of one fine-level residual R(u) (rocprofv3 FETCH_SIZE / WRITE_SIZE)\n\n")
+        f.write(f"Commands (repository root, on one MI355X):\n\n    {command}\n\n")
+        f.write(f"Calibration: a plain device copy of {copy_mib} MiB reads FETCH_SIZE = {f_copy:.0f} KiB and "
+                f"WRITE_SIZE = {w_copy:.0f} KiB; scale factors {fs:.3f} (fetch) and {ws:.3f} (write).  The last "
+                f"{R} residuals of the run are counted.\n\n")
+        f.write("| kernel | fetch MB | write MB |\n|---|---|---|\n")
+        for k, v in per.items():
+            f.write(f"| {k} | {v['fetch'] / 1e6:.2f} | {v['write'] / 1e6:.2f} |\n")
+        f.write(f"\nTotal {total / 1e6:.2f} MB per residual against the surveyed algorithmic {alg_bytes / 1e6:.2f} MB "
+                f"(160 B per node + 160 B per element face node): {total / alg_bytes:.2f} x.\n")
+    print(json.dumps(out))
+
+
+def kernel_stats(path, title, command):
+    """Per-kernel table (calls, total, average, share) of a --kernel-trace run: the CSV statistics when
+    present, else the dispatch table of the rocpd database."""
+    rows = []
+    found = glob.glob(os.path.join(path, "**", "*kernel_stats.csv"), recursive=True)
+    if found:
+        with open(found[0], newline="") as f:
+            for r in csv.DictReader(f):
+                rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"])))
+    else:
+        import sqlite3
+        db = glob.glob(os.path.join(path, "**", "*results.db"), recursive=True)[0]
+        con = sqlite3.connect(db)
+        for name, n, tot in con.execute("select name, count(*), sum(end - start) from kernels group by name"):
+            rows.append((name, int(n), float(tot)))
+    tot = sum(r[2] for r in rows)
+    rows.sort(key=lambda r: -r[2])
+    lines = [f"# rocprofv3 kernel statistics: {title}", "#", "# command (repository root, TMPDIR=/tmp, one MI355X):",
+             f"#   {command}", "#",
+             f"{'kernel':58s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}"]
+    for name, n, t in rows[:30]:
+        nm = name.replace("void ", "").split("(")[0][:58]
+        lines.append(f"{nm:58s} {n:7d} {t / 1e6:10.3f} {t / n / 1e3:10.2f} {100 * t / tot:6.2f}")
+    lines.append(f"{'all kernels':58s} {sum(r[1] for r in rows):7d} {tot / 1e6:10.3f}")
+    return "\n".join(lines) + "\n"
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--kernel", required=True)
-    ap.add_argument("--copy-mib", type=int, required=True)
+    ap.add_argument("--stats", default=None, help="summarise a --kernel-trace output directory")
+    ap.add_argument("--title", default="")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--kernel")
+    ap.add_argument("--residual", type=int, default=0, help="per residual: the last R residuals of the run")
+    ap.add_argument("--alg-bytes", type=float, default=0.0)
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", default="")
     ap.add_argument("--alg-json", default=None,
                     help="output of profile_plate --alg: compulsory bytes per launch of the same launches")
     ap.add_argument("--kind", default=None, help="kernel kind in that JSON (div, grad, ...)")
     args = ap.parse_args()
+    if args.stats:
+        txt = kernel_stats(args.stats, args.title, args.command)
+        with open(args.out, "w") as f:
+            f.write(txt)
+        print(txt)
+        return 0
+    if args.residual:
+        residual_traffic(args.fetch, args.write, args.residual, args.copy_mib, args.out, args.command, args.alg_bytes)
+        return 0
     f_avg, n, f_copy = _per_kernel(_rows(args.fetch), args.kernel)
     w_avg, n2, w_copy = _per_kernel(_rows(args.write), args.kernel)
     copy_kib = args.copy_mib * 1024.0

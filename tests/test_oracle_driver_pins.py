@@ -242,3 +242,30 @@ def test_fmg_threshold_crossed_after_two_cycles(oracle_mod):
     _, _, _, _, fmg = o.solve_record(wl.orders, wl.Q, None, caps=caps, tol=-1.0, max_cycles=4, beta_pre=2,
                                      beta_post=2, beta_coarse=bc, fmg=1, fmg_threshold=theta)
     assert fmg[0] == 2
+
+
+def test_step_formula_leaves_low_orders_past_rk3_stability(oracle_mod):
+    """Cause of cycles that diverge while RK3 on the finest level alone stays finite (Sec. 2 step limits,
+    Sec. 3.1 smoothing on every level): the printed limits scale with N^2 and N^4, while the spectral radius of
+    the DG operator grows like (N+1)^2 and (N+1)^4, so one pair of constants is relatively larger at low orders
+    -- (3/2)^4 ~ 5 times at order 2 against (6/5)^4 ~ 2 at order 5 for the viscous limit.  On the same
+    periodic box at Re 100: C = 0.6 is stable for RK3 sweeps at order 5 and blows up at order 2 within 50
+    sweeps; C = 0.3 is stable at order 2.  The coarse levels of a V-cycle smooth at their own orders with
+    their own (larger) steps, so a cycle diverges at constants its finest level tolerates."""
+    base = I.box_mesh((2, 2, 2), (-1, -1, -1), (1, 1, 1), M=(1, 1, 1), periodic=(True, True, True))
+
+    def sweeps(N, C, n):
+        ph = I.Physics(mach=0.2, reynolds=100.0, family=I.FAMILY_LG, cfl_adv=C, cfl_visc=C)
+        orders = I.uniform_orders(base.K, (N, N, N))
+        o = oracle_mod.Oracle(base, ph)
+        Q = I.perturbed_freestream(int(I.node_offsets(orders)[-1]), 0.2, 1e-2, 5)
+        r0 = np.abs(o.residual(orders, Q)).max()
+        Q = o.smooth(orders, Q, None, sweeps=n)
+        return r0, np.abs(o.residual(orders, Q)).max()
+
+    r0, r = sweeps(5, 0.6, 150)
+    assert np.isfinite(r) and r < 0.1 * r0
+    r0, r = sweeps(2, 0.6, 50)
+    assert not np.isfinite(r) or r > 1e6 * r0
+    r0, r = sweeps(2, 0.3, 150)
+    assert np.isfinite(r) and r < 0.1 * r0
