@@ -408,10 +408,14 @@ def solve_bench(args) -> dict:
 
     wl = I.config_plate()
     ctx = pmg.Context(0)
-    mg = pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4, precision=args.solve_precision)
+    b1, b2, bc = args.solve_beta
+    paper = args.solve_tuning or args.solve_fmg > 0
+    mg = pmg.MG(beta_pre=b1, beta_post=b2, beta_coarse=bc, precision=args.solve_precision,
+                tuning=int(args.solve_tuning), max_repeats=args.solve_max_repeats)
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
-    s = pmg.Solver(ctx, pmg.Mesh(ctx, wl.mesh), wl.orders, wl.phys, mg)
+    mesh = pmg.Mesh(ctx, wl.mesh)
+    s = pmg.Solver(ctx, mesh, wl.orders, wl.phys, mg)
     s.set_graph(True)
     Q = s.freestream()
     torch.cuda.synchronize()
@@ -421,9 +425,21 @@ def solve_bench(args) -> dict:
     cycles, r = 0, r0
     hist = [(0, r0)]
     t0 = time.perf_counter()
+    if args.solve_fmg > 0:
+        # the FMG start (Sec. 3.1.1) with the same smoothing, once, on a solver that has it
+        sf = pmg.Solver(ctx, mesh, wl.orders, wl.phys, pmg.MG(beta_pre=b1, beta_post=b2, beta_coarse=bc, fmg=1,
+                                                             fmg_threshold=args.solve_fmg, tuning=int(args.solve_tuning),
+                                                             max_repeats=args.solve_max_repeats))
+        # the solve stops on the finest level as soon as its residual is below the FMG threshold
+        c, r = sf.solve(Q, None, tol=args.solve_fmg, max_cycles=args.solve_max_cycles, raise_not_converged=False)
+        del sf
+        cycles += c
+        hist.append((cycles, r))
+        print(f"solve: FMG start, {cycles} cycles, residual {r:.3e}, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     while r >= args.solve_tol and cycles < args.solve_max_cycles and time.perf_counter() - t0 < args.solve_max_s:
-        if args.solve_precision == 1:
-            # mixed precision: the solver's own precision switch decides per cycle
+        if args.solve_precision == 1 or paper:
+            # the solve driver: mixed precision switch, residual-based smoothing tuning
             c, r = s.solve(Q, None, tol=args.solve_tol, max_cycles=chunk, raise_not_converged=False)
         else:
             r = s.vcycle(Q, None, n_cycles=chunk, norm=True)
@@ -439,7 +455,10 @@ def solve_bench(args) -> dict:
            "data": "synthetic",
            "config": {"workload": "flat-plate boundary layer: 64x32x1 stretched hexes (ratio 1.1), quadratic "
                                   "mapping, N=(6,6,1) Gauss, Mach 0.2, Re_L 1e5, wall + far field; far-field start",
-                      "dof": s.n_nodes, "tol": args.solve_tol, "vcycle": "levels 6..1, beta 2/2/4, graph replay",
+                      "dof": s.n_nodes, "tol": args.solve_tol,
+                      "vcycle": f"levels 6..1, beta {b1}/{b2}/{bc}" + (" (tuned, Sec. 3.1.2, at most "
+                                f"{args.solve_max_repeats} repetitions)" if args.solve_tuning else ", graph replay")
+                                + (f", FMG start to {args.solve_fmg}" if args.solve_fmg > 0 else ""),
                       "norm_every": chunk},
            "converged": bool(r < args.solve_tol), "cycles": cycles, "wall_s": wall, "residual": r,
            "initial_residual": r0, "setup_s": setup, "ms_per_cycle": 1e3 * wall / max(cycles, 1),
@@ -766,6 +785,10 @@ def main() -> int:
     ap.add_argument("--solve-max-cycles", type=int, default=400000)
     ap.add_argument("--solve-max-s", type=float, default=1000.0)
     ap.add_argument("--solve-precision", type=int, default=0)
+    ap.add_argument("--solve-beta", type=int, nargs=3, default=[2, 2, 4], metavar=("PRE", "POST", "COARSE"))
+    ap.add_argument("--solve-tuning", action="store_true", help="residual-based smoothing tuning (Sec. 3.1.2)")
+    ap.add_argument("--solve-max-repeats", type=int, default=10)
+    ap.add_argument("--solve-fmg", type=float, default=0.0, help="FMG start to this residual (Sec. 3.1.1)")
     ap.add_argument("--compare", action="store_true", help="RK3 against FAS: speed-up at equal residual")
     ap.add_argument("--sphere", action="store_true", help="sphere drag at Re_D 200 (soft physics check)")
     ap.add_argument("--sphere-order", type=int, default=4)

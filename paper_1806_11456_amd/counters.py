@@ -9,8 +9,8 @@ largest copy dispatch): a copy of B bytes reads B and writes B.  The result is w
 bench.py, which reports it only while the kernel sources still hash to the recorded value) and as a short
 Markdown summary.
 
-    python -m paper_1806_11456_amd.counters --fetch DIR --write DIR --kernel k_div --copy-mib 1024 \\
-        --out profiles/k_div_plate64x32_N661_counters.json --command "..."
+    python -m paper_1806_11456_amd.counters --fetch DIR --write DIR --residual 10 --alg-bytes B \\
+        --out profiles/residual_plate64x32_counters.json --command "..."
 """
 from __future__ import annotations
 
@@ -152,7 +152,7 @@ def main() -> int:
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", default="")
     ap.add_argument("--alg-json", default=None,
-                    help="output of profile_plate --alg: compulsory bytes per launch of the same launches")
+                    help="JSON with the compulsory bytes per launch of the same launches ({kind: {...}})")
     ap.add_argument("--kind", default=None, help="kernel kind in that JSON (div, grad, ...)")
     args = ap.parse_args()
     if args.stats:

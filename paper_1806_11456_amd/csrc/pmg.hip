@@ -827,7 +827,7 @@ static void op_eval(const pmg_solver_s* s, Level& L, const T* Q, bool isolated, 
                   k_face2c<T><<<L.nfctiles, PMG_FACE_TILE, 0, st>>>(D, L.d_fcrec, W.qf, W.fvn, W.Phi));
     if (L.nf1tiles > 0)
       PROF_LAUNCH(s, PK_FACE2, st, (17 * ncf + 4 * (nm - cm) + 5 * ncf) * w,
-                  k_face2<T><<<L.nf1tiles, PMG_FACE_TILE, 34 * PMG_FACE_TILE * sizeof(T), st>>>(D, L.d_f1list, W.qf,
+                  k_face2<T><<<L.nf1tiles, PMG_FACE_TILE, 17 * PMG_FACE_TILE * sizeof(T), st>>>(D, L.d_f1list, W.qf,
                                                                                            W.gf, W.Phi));
   }
   // divergence: Q, grad W, J a, 1/J, Phi in; the epilogue's own arrays
