@@ -11,6 +11,7 @@
 #include <thread>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -83,6 +84,14 @@ inline int cdiv(size_t a, int b) { return (int)((a + b - 1) / b); }
 // Bytes the library has requested from hipMalloc and not yet freed (all handles, all devices).
 std::atomic<long long> g_dev_bytes{0};
 
+// Debug mode (environment PMG_POISON=1, read at every allocation): fresh device allocations are filled with
+// all-ones bytes, a NaN in FP64 and FP32, so a kernel that reads memory nothing has written yet turns its
+// results non-finite instead of silently using whatever the allocator left there.
+static bool poison_allocations() {
+  const char* e = getenv("PMG_POISON");
+  return e && e[0] == '1';
+}
+
 struct DevArena {
   std::vector<void*> ptrs;
   long long bytes = 0;
@@ -91,6 +100,7 @@ struct DevArena {
     if (n == 0) n = 1;
     void* p = nullptr;
     HIPCHECK(hipMalloc(&p, n * sizeof(T)));
+    if (poison_allocations()) HIPCHECK(hipMemset(p, 0xff, n * sizeof(T)));
     ptrs.push_back(p);
     bytes += (long long)(n * sizeof(T));
     g_dev_bytes += (long long)(n * sizeof(T));
