@@ -100,9 +100,13 @@ typedef struct {
                                 (0 = 4) */
   int32_t guard;             /* divergence guard of pmg_solve / pmg_batch_solve: 0 off; n > 0: a problem whose
                                 residual check is non-finite or grew more than 1e4-fold over one cycle gets
-                                back its state of the previous check and both explicit step constants halved,
-                                at most n times (then PMG_ERR_NONPHYSICAL as without the guard).  The halved
-                                constants stay with the solver (pmg_guard_stats). */
+                                back its state of the previous check (of the start of the call if it fails
+                                again before an accepted check) and both explicit step constants halved, at
+                                most n times.  A problem that still fails keeps its last accepted state:
+                                pmg_solve returns PMG_ERR_NONPHYSICAL; pmg_batch_solve freezes it, finishes
+                                the others, reports its residual as NaN and returns PMG_ERR_NONPHYSICAL (its
+                                outputs filled).  The halved constants stay with the solver
+                                (pmg_guard_stats).  Device memory: two copies of the finest state. */
 } pmg_mg_params;
 
 const char* pmg_last_error(void);

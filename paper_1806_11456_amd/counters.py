@@ -24,16 +24,13 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-# host-only parts of the library that define and launch no kernel of the timed step (adaptation and the
-# wall-force diagnostic): editing them does not change what the counters measured
-HOST_ONLY = ("adapt.inc", "functionals.inc")
-
-
 def source_hash() -> str:
-    """SHA-256 over the HIP sources that define or launch the kernels of the timed step."""
+    """SHA-256 over the device sources: the kernels (kernels_*.inc) and their device helpers (device.h).  The
+    host library (launch sizes, drivers) is not hashed."""
     h = hashlib.sha256()
     for path in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
-        if os.path.basename(path) in HOST_ONLY:
+        base = os.path.basename(path)
+        if not (base == "device.h" or (base.startswith("kernels_") and base.endswith(".inc"))):
             continue
         with open(path, "rb") as f:
             h.update(os.path.basename(path).encode())

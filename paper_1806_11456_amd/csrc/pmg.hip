@@ -327,6 +327,7 @@ struct pmg_solver_s {
   std::vector<int> fp32_cycles;              // per problem: cycles of the last solve with FP32 coarse levels
   std::vector<int> halvings;                 // per problem: step-constant halvings by the divergence guard
   double* d_Qbak = nullptr;                  // [5][nn] the state at the last accepted check (divergence guard)
+  double* d_Qstart = nullptr;                // [5][nn] the state at the start of the guarded solve call
   // the shared face-trace array holds the traces of this state on this level (launch-order bookkeeping:
   // k_trace is skipped when the next evaluation is of the same state on the same level)
   mutable const Level* qf_level = nullptr;
@@ -1599,7 +1600,7 @@ static double solver_footprint(const pmg_mesh_s* m, const int32_t* orders, const
     }
   }
   b += sizeof(Phys) + 4.0 * K + 3 * 4.0 + 8.0 * NSLOTS + 8.0 * K + 3 * 5 * 8.0 * nn_top;  // solver arrays
-  if (mg && mg->guard > 0) b += 5 * 8.0 * nn_top;  // the divergence guard's state copy (first guarded solve)
+  if (mg && mg->guard > 0) b += 2 * 5 * 8.0 * nn_top;  // the divergence guard's two state copies
   if (transient) *transient = 12.0 * 8.0 * nn_top;
   if (switch_extra) *switch_extra = extra;
   return b;
@@ -1910,44 +1911,70 @@ struct MixedState {
 
 // Divergence guard of the solve drivers (mg.guard > 0).  At every residual check, a problem whose residual is
 // no longer finite, or grew more than 1e4-fold over the last cycle, gets back its state of the previous check
-// and continues with both explicit step constants halved (at most mg.guard times; then the solve fails as
-// without the guard).  The halved constants stay with the solver.  The state of every problem is copied at
-// each accepted check (one device copy of the finest state; a V-cycle costs far more).
+// (or, when it fails again before any accepted check, its state at the start of the call) and continues with
+// both explicit step constants halved, at most mg.guard times; a problem that still fails then keeps its last
+// accepted state and is reported as failed (pmg_solve fails; pmg_batch_solve freezes it and carries on with
+// the others).  The halved constants stay with the solver.  The state of every problem is copied at each
+// accepted check (one device copy of the finest state; a V-cycle costs far more).
 struct DivGuard {
   pmg_solver_s* s;
   hipStream_t st;
-  std::vector<double> r_ok;  // residual at the last accepted check
+  std::vector<double> r_ok, r_start;  // residuals at the last accepted check and at the start of the call
+  std::vector<int> fails;             // per problem: failures since its last accepted check
   bool first = true;
-  DivGuard(pmg_solver_s* s_, hipStream_t st_) : s(s_), st(st_), r_ok(s_->nprob, 0.0) {
-    if (s->mg.guard > 0 && !s->d_Qbak) s->d_Qbak = s->arena.alloc<double>(5 * (size_t)s->top->nn);
+  DivGuard(pmg_solver_s* s_, hipStream_t st_)
+      : s(s_), st(st_), r_ok(s_->nprob, 0.0), r_start(s_->nprob, 0.0), fails(s_->nprob, 0) {
+    if (s->mg.guard > 0 && !s->d_Qbak) {
+      s->d_Qbak = s->arena.alloc<double>(5 * (size_t)s->top->nn);
+      s->d_Qstart = s->arena.alloc<double>(5 * (size_t)s->top->nn);
+    }
   }
-  // r: this check's residuals (restored problems get their previous residual back); advanced: the problems the
-  // last cycle moved.  Returns false when a problem has used up its halvings (the caller fails as unguarded).
-  bool check(std::vector<double>& r, const std::vector<int>& advanced, double* Q) {
-    if (s->mg.guard <= 0) return true;
+  void restore(int p, const double* from, double* Q) {
+    const Level& T = *s->top;
+    const size_t n0 = T.off[s->prob_elem[p]], n1 = T.off[s->prob_elem[p + 1]];
+    for (int v = 0; v < 5; v++)
+      HIPCHECK(hipMemcpyAsync(Q + (size_t)v * T.nn + n0, from + (size_t)v * T.nn + n0, (n1 - n0) * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+  }
+  // r: this check's residuals (restored problems get the residual of the state they got back); advanced: the
+  // problems the last cycle moved.  Returns the problems that used up their halvings (restored to their last
+  // accepted state).
+  std::vector<int> check(std::vector<double>& r, const std::vector<int>& advanced, double* Q) {
+    std::vector<int> failed;
+    if (s->mg.guard <= 0) return failed;
     const Level& T = *s->top;
     bool restored = false;
     for (int p = 0; p < s->nprob && !first; p++) {
       if (!advanced[p]) continue;
-      if (r[p] == r[p] && !(r[p] > 1e4 * r_ok[p])) continue;
-      if (s->halvings[p] >= s->mg.guard) return false;
+      if (r[p] == r[p] && !(r[p] > 1e4 * r_ok[p])) {
+        fails[p] = 0;
+        continue;
+      }
+      restored = true;
+      if (s->halvings[p] >= s->mg.guard) {
+        restore(p, s->d_Qbak, Q);
+        r[p] = r_ok[p];
+        failed.push_back(p);
+        continue;
+      }
       s->halvings[p]++;
-      const size_t n0 = T.off[s->prob_elem[p]], n1 = T.off[s->prob_elem[p + 1]];
-      for (int v = 0; v < 5; v++)
-        HIPCHECK(hipMemcpyAsync(Q + (size_t)v * T.nn + n0, s->d_Qbak + (size_t)v * T.nn + n0,
-                                (n1 - n0) * sizeof(double), hipMemcpyDeviceToDevice, st));
+      const bool again = ++fails[p] >= 2;
+      restore(p, again ? s->d_Qstart : s->d_Qbak, Q);
+      r[p] = again ? r_start[p] : r_ok[p];
       s->phys[p].cfl_adv *= 0.5;
       s->phys[p].cfl_visc *= 0.5;
       HIPCHECK(hipStreamSynchronize(st));
       HIPCHECK(hipMemcpy(s->d_ptab + p, &s->phys[p], sizeof(Phys), hipMemcpyHostToDevice));
-      r[p] = r_ok[p];
-      restored = true;
     }
     if (restored) traces_stale(s);
+    if (first) {
+      r_start = r;
+      copy(s->d_Qstart, (const double*)Q, 5 * (size_t)T.nn, st);
+    }
     for (int p = 0; p < s->nprob; p++) r_ok[p] = r[p];
     first = false;
     copy(s->d_Qbak, (const double*)Q, 5 * (size_t)T.nn, st);
-    return true;
+    return failed;
   }
 };
 
@@ -1993,7 +2020,7 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
       residual(s, *s->top, (const double*)Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
       r = read_slot(s, SLOT_NORM, st);
       std::vector<double> rv(1, r);
-      if (!dg.check(rv, one, Q_dev)) throw PmgError(PMG_ERR_NONPHYSICAL, "diverged after every step halving");
+      if (!dg.check(rv, one, Q_dev).empty()) throw PmgError(PMG_ERR_NONPHYSICAL, "diverged after every step halving");
       r = rv[0];
       s->history.push_back(r);
       if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
@@ -2033,13 +2060,14 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
     for (auto& m : ms) m.f32 = mixed;
     std::vector<double> r(n, 0.0);
     DivGuard dg(s, st);
+    std::vector<int> dead(n, 0);  // problems the guard gave up on: frozen at their last accepted state
     for (;;) {
       residual(s, *s->top, (const double*)Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);  // every problem
       r = read_slots(s, SLOT_NORM, st);
-      if (!dg.check(r, active, Q_dev))
-        throw PmgError(PMG_ERR_NONPHYSICAL, "a problem diverged after every step halving");
+      for (int p : dg.check(r, active, Q_dev)) dead[p] = 1;
       int n32 = 0, n64 = 0;
       for (int p = 0; p < n; p++) {
+        if (dead[p]) active[p] = 0;
         if (r[p] != r[p]) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual in problem " + std::to_string(p));
         if (active[p] && (r[p] < tol || cyc[p] >= max_cycles)) active[p] = 0;  // converged problems freeze
         if (active[p]) ms[p].update(r[p], patience);
@@ -2065,11 +2093,16 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
     }
     s->fp32_cycles = c32;
     bool all = true;
+    std::string gave_up;
     for (int p = 0; p < n; p++) {
       if (cycles_out) cycles_out[p] = cyc[p];
-      if (res_inf_out) res_inf_out[p] = r[p];
+      if (res_inf_out) res_inf_out[p] = dead[p] ? (double)NAN : r[p];
       all = all && r[p] < tol;
+      if (dead[p]) gave_up += (gave_up.empty() ? "" : ", ") + std::to_string(p);
     }
+    if (!gave_up.empty())
+      throw PmgError(PMG_ERR_NONPHYSICAL, "diverged after every step halving (frozen at their last accepted "
+                                          "state, residual reported as NaN): problems " + gave_up);
     if (!all) throw PmgError(PMG_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance in some problem");
   });
   return rc;

@@ -551,13 +551,16 @@ class Batch(Solver):
         _check(lib().pmg_batch_norms(self.h, _ptr(Q), _ptr(S), r.ctypes.data_as(C.POINTER(C.c_double)), _stream()))
         return r
 
-    def solve_all(self, Q, S=None, tol=1e-9, max_cycles=100, raise_not_converged=True):
+    def solve_all(self, Q, S=None, tol=1e-9, max_cycles=100, raise_not_converged=True, raise_failed=True):
+        """Batched solve (pmg_batch_solve): per-problem cycles and residuals.  raise_failed=False returns the
+        outputs also when the divergence guard gave up on some problems (their residual NaN)."""
         cyc = np.zeros(self.n, dtype=np.int32)
         r = np.zeros(self.n)
         rc = lib().pmg_batch_solve(self.h, _ptr(Q), _ptr(S), float(tol), int(max_cycles),
                                    cyc.ctypes.data_as(C.POINTER(C.c_int32)), r.ctypes.data_as(C.POINTER(C.c_double)),
                                    _stream())
-        if rc != 0 and (rc != 5 or raise_not_converged):
+        if rc != 0 and not (rc == 5 and not raise_not_converged) and not (rc == 4 and not raise_failed
+                                                                        and self.mg.guard > 0):
             _check(rc)
         return cyc, r
 

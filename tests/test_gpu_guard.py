@@ -62,3 +62,30 @@ def test_guard_restores_and_halves(ctx):
         assert hs[0] == h[p], (p, hs, h)
         assert cs == cyc[p] and rs == r[p], (p, cs, rs, cyc[p], r[p])
         assert np.array_equal(np_(b.part(Q, p)), np_(Qs)), p
+
+
+def test_guard_gives_up_and_freezes(ctx):
+    """With too few halvings allowed the guard gives up on the unstable problem: it keeps its last accepted
+    state (finite), its residual is reported as NaN, the call fails, and the other problems still run every
+    cycle, bitwise as in their own solves."""
+    from paper_1806_11456_amd import pmg
+    probs = _problems()
+    meshes = [pmg.Mesh(ctx, w.mesh) for w in probs]
+    b = pmg.Batch(ctx, meshes, [w.orders for w in probs], [w.phys for w in probs], pmg.MG(guard=2, **MG))
+    Q = b.tensor(np.concatenate([w.Q for w in probs], axis=1))
+    with pytest.raises(pmg.PmgError, match="problems 1"):
+        b.solve_all(Q, None, tol=1e-30, max_cycles=12, raise_not_converged=False)
+    b2 = pmg.Batch(ctx, meshes, [w.orders for w in probs], [w.phys for w in probs], pmg.MG(guard=2, **MG))
+    Q2 = b2.tensor(np.concatenate([w.Q for w in probs], axis=1))
+    cyc, r = b2.solve_all(Q2, None, tol=1e-30, max_cycles=12, raise_not_converged=False, raise_failed=False)
+    h, _ = b2.guard_stats()
+    print(f"[guard] gave up: cycles {list(cyc)}, residuals {list(r)}, halvings {h.tolist()}")
+    assert np.isnan(r[1]) and np.isfinite(r[[0, 2]]).all() and h[1] == 2
+    assert cyc[0] == cyc[2] == 12 and cyc[1] < 12
+    assert np.isfinite(np_(b2.part(Q2, 1))).all()
+    for p in (0, 2):
+        s = pmg.Solver(ctx, meshes[p], probs[p].orders, probs[p].phys, pmg.MG(guard=2, **MG))
+        Qs = s.tensor(probs[p].Q)
+        cs, rs = s.solve(Qs, None, tol=1e-30, max_cycles=12, raise_not_converged=False)
+        assert cs == cyc[p] and rs == r[p]
+        assert np.array_equal(np_(b2.part(Q2, p)), np_(Qs)), p
