@@ -109,6 +109,43 @@ def residual_traffic(fetch_dir, write_dir, R, copy_mib, out_path, command, alg_b
     print(json.dumps(out))
 
 
+def sq_summary(dirs, R, title, command, alg_flops):
+    """Per-kernel instruction and stall counters (SQ block) of the last R residuals of profile_residual.py runs,
+    one directory per counter pass: waves, the fraction of wave time spent waiting and issuing VALU / LDS work,
+    instructions per wave and FP64 VALU flops (the SQ_INSTS_VALU_FLOPS_FP64 count times the 64 lanes of a wave)."""
+    agg = {}
+    for d in dirs:
+        for r in _last_residuals(_rows(d), R):
+            k = _base(r["Kernel_Name"])
+            agg.setdefault(k, {})
+            agg[k][r["Counter_Name"]] = agg[k].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"]) / R
+    g = lambda k, c: agg[k].get(c, 0.0)
+    lines = [f"# SQ counters per fine-level residual: {title}", "",
+             "Commands (repository root, TMPDIR=/tmp, one MI355X; two counter passes):", "", f"    {command}", "",
+             "| kernel | waves | wait / wave time | VALU / wave time | LDS / wave time | VALU instr / wave | "
+             "LDS instr / wave | VMEM rd / wave | FP64 VALU GFLOP | MFMA F64 instr |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    tot_fl = 0.0
+    for k in sorted(agg, key=lambda k: -g(k, "SQ_WAVE_CYCLES")):
+        if k not in RESIDUAL_KERNELS:
+            continue
+        w, wc = g(k, "SQ_WAVES"), g(k, "SQ_WAVE_CYCLES")
+        fl = 64.0 * g(k, "SQ_INSTS_VALU_FLOPS_FP64")
+        tot_fl += fl
+        frac = lambda c: g(k, c) / wc if wc else 0.0
+        per = lambda c: g(k, c) / w if w else 0.0
+        lines.append(f"| {k} | {w:.0f} | {frac('SQ_WAIT_ANY'):.2f} | {frac('SQ_ACTIVE_INST_VALU'):.2f} | "
+                     f"{frac('SQ_ACTIVE_INST_LDS'):.2f} | {per('SQ_INSTS_VALU'):.0f} | {per('SQ_INSTS_LDS'):.0f} | "
+                     f"{per('SQ_INSTS_VMEM_RD'):.0f} | {fl / 1e9:.3f} | {g(k, 'SQ_INSTS_VALU_MFMA_F64'):.0f} |")
+    lines += ["", f"FP64 VALU flops per residual as counted {tot_fl / 1e9:.3f} GFLOP (counter x 64 lanes) against the "
+                  f"surveyed model's {alg_flops / 1e9:.3f} GFLOP.  The SQ counters are collected per shader engine and "
+                  "the wave counts here are a fraction (1/5 to 1/10) of the waves the launches create, so absolute "
+                  "counts (waves, flops) are not compared; the ratios within a kernel (time waiting, VALU and LDS "
+                  "issue, instructions per wave) are.  No FP64 MFMA instruction runs: the contractions use the FP64 "
+                  "vector units, which are busy 6-17 % of the wave time, so matrix cores would not shorten them."]
+    return "\n".join(lines) + "\n"
+
+
 def kernel_stats(path, title, command):
     """Per-kernel table (calls, total, average, share) of a --kernel-trace run: the CSV statistics when
     present, else the dispatch table of the rocpd database."""
@@ -139,6 +176,8 @@ def kernel_stats(path, title, command):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", default=None, help="summarise a --kernel-trace output directory")
+    ap.add_argument("--sq", nargs="+", default=None, help="SQ counter pass directories to summarise per residual")
+    ap.add_argument("--alg-flops", type=float, default=0.0)
     ap.add_argument("--title", default="")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -152,6 +191,12 @@ def main() -> int:
                     help="JSON with the compulsory bytes per launch of the same launches ({kind: {...}})")
     ap.add_argument("--kind", default=None, help="kernel kind in that JSON (div, grad, ...)")
     args = ap.parse_args()
+    if args.sq:
+        txt = sq_summary(args.sq, args.residual or 10, args.title, args.command, args.alg_flops)
+        with open(args.out, "w") as f:
+            f.write(txt)
+        print(txt)
+        return 0
     if args.stats:
         txt = kernel_stats(args.stats, args.title, args.command)
         with open(args.out, "w") as f:
