@@ -181,6 +181,16 @@ def timed(step, steps: int, warmup: int) -> float:
     return time.perf_counter() - t0
 
 
+def tile_desc(s):
+    """The autotuned element tiles of each level, finest first: node target, '+split' when the level's tiles
+    are launched per size class."""
+    out = []
+    for l in reversed(range(s.level_info(-1))):  # level 0 is the coarsest
+        t, sp = s.level_tile_choice(-1, l)
+        out.append(f"{t}{'+split' if sp else ''}")
+    return "autotuned per level, finest first: " + ", ".join(out)
+
+
 def batch_line(args, wls) -> dict:
     """Configuration of 64 independent problems: batched solve-driver iterations (mixed precision, graph
     replay, autotuned tiles, divergence guard)."""
@@ -210,8 +220,8 @@ def batch_line(args, wls) -> dict:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     halv, _ = b.guard_stats()
-    print(f"batch: guard halvings per problem {halv.tolist()}; given up: {np.flatnonzero(np.isnan(r)).tolist()}",
-          file=sys.stderr, flush=True)
+    print(f"batch: guard halvings per problem {halv.tolist()}; given up: {np.flatnonzero(np.isnan(r)).tolist()}; "
+          f"cycles on FP32 coarse levels per problem {b.fp32_cycles().tolist()}", file=sys.stderr, flush=True)
     per_cycle = 3 * (b1 + b2) + 1
     # fine-level evaluations done: every problem's cycles (a problem the guard gave up on stops cycling) and the
     # batched residual checks, which cover every problem
@@ -225,7 +235,7 @@ def batch_line(args, wls) -> dict:
                        "dof": b.n_nodes, "problems": len(wls),
                        "step": f"batched solve-driver iteration: FP64 residual check + divergence guard + one FAS "
                                f"V-cycle (levels 5..1, beta {b1}/{b2}/{bc}), FP32 coarse levels, graph replay",
-                       "tiles": "autotuned per level", "fine_residual_evals_per_step": per_cycle + 1,
+                       "tiles": tile_desc(b), "fine_residual_evals_per_step": per_cycle + 1,
                        "setup_s": round(setup, 2)},
             "guard_halvings": int(halv.sum()), "problems_halved": int((halv > 0).sum()),
             "problems_given_up": int(np.isnan(r).sum()), "cycles_run": int(np.sum(cyc)),
@@ -272,7 +282,7 @@ def ogrid_line(args) -> dict:
                               "dof": s.n_nodes,
                               "step": f"solve-driver iteration (residual checks + guard + FAS V-cycle, levels 7..1, "
                                       f"beta {b1}/{b2}/{bc}) + isolated anisotropic 3V tau estimate of the state",
-                              "fine_residual_evals_per_step": evals},
+                              "tiles": tile_desc(s), "fine_residual_evals_per_step": evals},
                    "guard_halvings": int(halv.sum()),
                    **residual_roofline(s, Q, [wl.orders], args.residual_loops, "ogrid8x13")}
         else:
@@ -312,7 +322,7 @@ def plate_line(args) -> dict:
                                    "mapping, N=(6,6,1) Gauss, Mach 0.2, Re_L 1e5, wall + far field",
                        "dof": s.n_nodes,
                        "step": f"isotropic FAS V-cycle (levels 6..1, beta {b1}/{b2}/{bc}) + anisotropic 3V "
-                               f"isolated tau", "fine_residual_evals_per_step": evals},
+                               f"isolated tau", "tiles": tile_desc(s), "fine_residual_evals_per_step": evals},
             **residual_roofline(s, Q, [wl.orders], args.residual_loops, "plate64x32")}
 
 

@@ -96,8 +96,11 @@ typedef struct {
                                 hierarchies stay FP64.  pmg_solve / pmg_batch_solve switch a problem to FP64
                                 coarse levels once its FP64 residual stops reaching new minima (the round-off
                                 floor of the FP32 correction), so the converged solution is an FP64 solution. */
-  int32_t mixed_patience;    /* precision 1: cycles without a new minimum of the residual before the switch
-                                (0 = 4) */
+  int32_t mixed_patience;    /* precision 1: stalled cycles before the switch (0 = 4).  A cycle is stalled when
+                                the residual reaches no new minimum, has fallen below its first value of the
+                                call, stays within twice its best and did not rise over the cycle (a floor
+                                hovers; a start-up transient rises cycle after cycle); a cycle the divergence
+                                guard rolled back restarts the count. */
   int32_t guard;             /* divergence guard of pmg_solve / pmg_batch_solve: 0 off; n > 0: a problem whose
                                 residual check is non-finite or grew more than 1e4-fold over one cycle gets
                                 back its state of the previous check (of the start of the call if it fails
@@ -316,9 +319,16 @@ pmg_status pmg_solve_stats(pmg_solver s, int32_t* fp32_cycles);
  */
 pmg_status pmg_set_graph(pmg_solver s, int enable);
 /* Tile autotuner: times the operator on every built level for element tiles of about 64, 128, 256 and 512
- * nodes and keeps the fastest (cached per context by the level's order-bucket histogram). */
+ * nodes, each launched either as one grid or split into classes by tile size (at most 64, 128, 256 nodes,
+ * larger) with a block size per class, and keeps the fastest (cached per context by the level's
+ * order-bucket histogram).  Results do not depend on the choice.  pmg_level_tiles returns a level's node
+ * target and (split, nullable) 1 when its tiles are launched per size class. */
 pmg_status pmg_autotune(pmg_solver s, void* stream);
-pmg_status pmg_level_tiles(pmg_solver s, int hierarchy, int level, int32_t* tile_target);
+pmg_status pmg_level_tiles(pmg_solver s, int hierarchy, int level, int32_t* tile_target, int32_t* split);
+/* Sets one level's element tiles by hand (tile_target 64, 128, 256 or 512 nodes; split 0 or 1, as above):
+ * waits for the device, rebuilds the level's tile arrays and drops the solver's captured graphs.  Results do
+ * not change.  PMG_ERR_INVALID_ARG for other values or a level out of range. */
+pmg_status pmg_set_tiles(pmg_solver s, int hierarchy, int level, int tile_target, int split);
 
 /*
  * Kernel timing with HIP events (diagnostics).  mask selects kernel kinds (bit k = kind k):

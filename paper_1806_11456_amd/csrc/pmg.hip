@@ -160,6 +160,12 @@ static int grad_lds_words(int nodes, int face_nodes) { return 13 * nodes + 7 * f
 // LDS of the divergence kernel: the nodal fluxes, and Phi at the face nodes (or the updated state at the nodes).
 static int div_lds_words(int nodes, int face_nodes) { return 15 * nodes + 5 * std::max(nodes, face_nodes); }
 
+// A range of a level's element tiles launched with one block size: the smallest of 64, 128, 256 threads that
+// holds the range's largest tile, one node per thread unless a tile is larger than 256 nodes (npt 2).
+struct TileClass {
+  int first = 0, count = 0, block = PMG_BLOCK, npt = 1, max_tile = 1, grad_words = 1, div_words = 1;
+};
+
 struct Level {
   int K = 0, nn = 0, nf = 0, nm = 0, fam = 0;
   int prec = PREC_F64;  // working precision of the operator and smoother on this level
@@ -170,7 +176,10 @@ struct Level {
   int nf1tiles = 0;                        // face tiles of p-nonconforming interfaces (mortar passes)
   int nfctiles = 0;                        // face tiles of conforming interfaces and boundaries
   int64_t nfl_conf = 0, nfl_bnd = 0, nfl_nc = 0;  // face nodes on conforming / boundary / mortar faces
-  int block = PMG_BLOCK;  // threads per element tile: the smallest of 64, 128, 256 that holds the largest tile
+  // launch ranges of the element tiles: one holding every tile, or (tile_split) one per block size, the tiles
+  // ordered by class and, within a class, by problem
+  std::vector<TileClass> tcls;
+  int tile_split = 0;
   DevArena arena;
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
   int *d_ord, *d_off, *d_fo, *d_node_elem, *d_elist, *d_mface, *d_ftile, *d_ftprob;
@@ -184,7 +193,7 @@ struct Level {
   std::vector<double> wall_w;
   int* d_wall_mn = nullptr;
   double* d_wall_w = nullptr;
-  int* d_ptile = nullptr;  // [nprob + 1]: the element tiles of each problem (contiguous)
+  int* d_ptile = nullptr;  // [tcls.size()][nprob + 1]: the element tiles of each problem within each class
   int4* d_tiles;
   FaceRec* d_faces;
   double *d_Ja, *d_invJ, *d_J, *d_Nout, *d_mgeo;  // geometry in FP64 (always kept)
@@ -202,9 +211,9 @@ struct Level {
     if constexpr (std::is_same<T, float>::value) return w32; else return w64;
   }
   size_t wsize() const { return prec == PREC_F32 ? sizeof(float) : sizeof(double); }
-  size_t lds_trace() const { return (size_t)5 * max_tile * wsize(); }
-  size_t lds_grad() const { return (size_t)grad_words * wsize(); }
-  size_t lds_div() const { return (size_t)div_words * wsize(); }
+  size_t lds_trace(const TileClass& c) const { return (size_t)5 * c.max_tile * wsize(); }
+  size_t lds_grad(const TileClass& c) const { return (size_t)c.grad_words * wsize(); }
+  size_t lds_div(const TileClass& c) const { return (size_t)c.div_words * wsize(); }
 };
 
 struct XferTiles {
@@ -360,13 +369,16 @@ static unsigned long long* slot_ptr(const pmg_solver_s* s, int slot) { return s-
 // Level construction (Sec. 2 geometry; tiles and faces)
 // ------------------------------------------------------------------------------------------------
 // Element tiles: elements bucketed by (problem, order triple), packed to about 'target' nodes (one element
-// when larger), so every tile has one order triple and one problem.
-static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
+// when larger), so every tile has one order triple and one problem.  'split': the tiles are launched in
+// classes by size (at most 64, 128, 256 nodes, larger), each with its own block size and LDS, so that a small
+// tile does not hold the idle lanes of the level's largest block; otherwise every tile is in one launch.
+static void build_tiles(const pmg_solver_s* s, Level& L, int target, int split = 0) {
   std::map<std::pair<int, int>, std::vector<int>> buckets;
   for (int e = 0; e < L.K; e++)
     buckets[{s->eprob[e], pack3(L.ord[3 * e] + 1, L.ord[3 * e + 1] + 1, L.ord[3 * e + 2] + 1)}].push_back(e);
   std::vector<int> elist;
   std::vector<int4> tiles;
+  std::vector<int> tgw, tdw;  // LDS words of each tile (gradient, divergence)
   int max_tile = 1, grad_words = 1, div_words = 1;
   for (auto& kv : buckets) {
     int key = kv.first.second;
@@ -379,12 +391,14 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
              (size_t)s->ctx->lds_max;
     };
     while (per > 1 && (per * npe > PMG_TILE_MAX || !lds_fits(per))) per--;
-    grad_words = std::max(grad_words, grad_lds_words(per * npe, per * fpe));
-    div_words = std::max(div_words, div_lds_words(per * npe, per * fpe));
     const auto& es = kv.second;
     for (size_t i = 0; i < es.size(); i += per) {
       int cnt = (int)std::min<size_t>(per, es.size() - i);
       tiles.push_back(make_int4((int)elist.size(), cnt, key, cnt * npe));
+      tgw.push_back(grad_lds_words(cnt * npe, cnt * fpe));
+      tdw.push_back(div_lds_words(cnt * npe, cnt * fpe));
+      grad_words = std::max(grad_words, tgw.back());
+      div_words = std::max(div_words, tdw.back());
       max_tile = std::max(max_tile, cnt * npe);
       for (int c = 0; c < cnt; c++) elist.push_back(es[i + c]);
     }
@@ -392,12 +406,44 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   REQUIRE(max_tile <= PMG_TILE_MAX, "element tile too large");
   REQUIRE((size_t)std::max(grad_words, div_words) * L.wsize() <= (size_t)s->ctx->lds_max,
           "element tile too large for the device's LDS");
-  std::vector<int> tprob(tiles.size()), eoff(elist.size()), efo(elist.size()), ptile(s->nprob + 1, 0);
+  // launch classes; a stable reorder by class keeps each class's tiles grouped by problem
+  auto block_of = [](int nodes) { return nodes <= 64 ? 0 : (nodes <= 128 ? 1 : (nodes <= PMG_BLOCK ? 2 : 3)); };
+  const int ncls = split ? 4 : 1;
+  std::vector<int> tcl(tiles.size(), 0);
+  if (split)
+    for (size_t t = 0; t < tiles.size(); t++) tcl[t] = block_of(tiles[t].w);
+  std::vector<int> order;
+  order.reserve(tiles.size());
+  std::vector<TileClass> cls(ncls);
+  for (int c = 0; c < ncls; c++) {
+    TileClass& C = cls[c];
+    C.first = (int)order.size();
+    for (size_t t = 0; t < tiles.size(); t++)
+      if (tcl[t] == c) {
+        order.push_back((int)t);
+        C.max_tile = std::max(C.max_tile, tiles[t].w);
+        C.grad_words = std::max(C.grad_words, tgw[t]);
+        C.div_words = std::max(C.div_words, tdw[t]);
+      }
+    C.count = (int)order.size() - C.first;
+    const int b = block_of(C.max_tile);
+    C.block = b == 0 ? 64 : (b == 1 ? 128 : PMG_BLOCK);
+    C.npt = b == 3 ? PMG_NPT : 1;
+  }
+  std::vector<int4> otiles(tiles.size());
+  for (size_t t = 0; t < order.size(); t++) otiles[t] = tiles[order[t]];
+  tiles.swap(otiles);
+  std::vector<int> tprob(tiles.size()), eoff(elist.size()), efo(elist.size()), ptile((size_t)ncls * (s->nprob + 1), 0);
   for (size_t t = 0; t < tiles.size(); t++) tprob[t] = s->eprob[elist[tiles[t].x]];
-  // buckets are ordered by problem first: each problem's tiles are one range
-  for (size_t t = 0; t < tiles.size(); t++) ptile[tprob[t] + 1] = (int)t + 1;
-  for (int p = 0; p < s->nprob; p++) ptile[p + 1] = std::max(ptile[p + 1], ptile[p]);
-  for (size_t t = 1; t < tiles.size(); t++) REQUIRE(tprob[t] >= tprob[t - 1], "element tiles not grouped by problem");
+  // buckets are ordered by problem first: within a class each problem's tiles are one range
+  for (int c = 0; c < ncls; c++) {
+    int* pt = ptile.data() + (size_t)c * (s->nprob + 1);
+    const int t0 = cls[c].first, t1 = cls[c].first + cls[c].count;
+    for (int p = 0; p <= s->nprob; p++) pt[p] = t0;
+    for (int t = t0; t < t1; t++) pt[tprob[t] + 1] = t + 1;
+    for (int p = 0; p < s->nprob; p++) pt[p + 1] = std::max(pt[p + 1], pt[p]);
+    for (int t = t0 + 1; t < t1; t++) REQUIRE(tprob[t] >= tprob[t - 1], "element tiles not grouped by problem");
+  }
   REQUIRE((int)tiles.size() <= L.K, "more element tiles than elements");
   for (size_t k = 0; k < elist.size(); k++) {
     eoff[k] = L.off[elist[k]];
@@ -428,7 +474,8 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target) {
   L.grad_words = grad_words;
   L.div_words = div_words;
   L.tile_target = target;
-  L.block = max_tile <= 64 ? 64 : (max_tile <= 128 ? 128 : PMG_BLOCK);
+  L.tile_split = split;
+  L.tcls = cls;
   L.dev.tiles = L.dev32.tiles = L.d_tiles;
   L.dev.elist = L.dev32.elist = L.d_elist;
   L.dev.eoff = L.dev32.eoff = L.d_eoff;
@@ -749,43 +796,69 @@ static DivArgs<T> div_args(int mode) {
   return a;
 }
 
-// Element-tile launches: the kernel instance whose block size is the level's (and, for the gradient and the
-// divergence, one node per thread unless a tile is larger than the block).
+// Element-tile launches: per launch class of the level's tiles, the kernel instance of the class's block size
+// (and, for the gradient and the divergence, one node per thread unless a tile is larger than the block),
+// the tile records and per-tile outputs offset to the class's first tile.
+template <class T>
+static LevelDevT<T> class_dev(const LevelDevT<T>& D, const TileClass& c) {
+  LevelDevT<T> Dc = D;
+  Dc.tiles = D.tiles + 2 * (size_t)c.first;
+  return Dc;
+}
+
 template <class T>
 static void launch_trace(const Level& L, const LevelDevT<T>& D, const T* Q, T* qf, hipStream_t st) {
-  const size_t lds = L.lds_trace();
-  if (L.block == 64) k_trace<T, 64><<<L.ntiles, 64, lds, st>>>(D, Q, qf);
-  else if (L.block == 128) k_trace<T, 128><<<L.ntiles, 128, lds, st>>>(D, Q, qf);
-  else k_trace<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf);
+  for (const TileClass& c : L.tcls) {
+    if (!c.count) continue;
+    const LevelDevT<T> Dc = class_dev(D, c);
+    const size_t lds = L.lds_trace(c);
+    if (c.block == 64) k_trace<T, 64><<<c.count, 64, lds, st>>>(Dc, Q, qf);
+    else if (c.block == 128) k_trace<T, 128><<<c.count, 128, lds, st>>>(Dc, Q, qf);
+    else k_trace<T, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, qf);
+  }
 }
 
 template <class T>
 static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const T* qf, const T* Ws, int isolated,
                         T* gW, T* gf, T* fvn, T* phi, hipStream_t st) {
-  const size_t lds = L.lds_grad();
-  if (L.block == 64) k_grad<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn, phi);
-  else if (L.block == 128)
-    k_grad<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn, phi);
-  else if (L.max_tile <= PMG_BLOCK)
-    k_grad<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn, phi);
-  else k_grad<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, qf, Ws, isolated, gW, gf, fvn, phi);
+  for (const TileClass& c : L.tcls) {
+    if (!c.count) continue;
+    const LevelDevT<T> Dc = class_dev(D, c);
+    const size_t lds = L.lds_grad(c);
+    if (c.block == 64) k_grad<T, 1, 64><<<c.count, 64, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
+    else if (c.block == 128)
+      k_grad<T, 1, 128><<<c.count, 128, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
+    else if (c.npt == 1)
+      k_grad<T, 1, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
+    else k_grad<T, PMG_NPT, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
+  }
 }
 
 template <class T>
 static void launch_div(const Level& L, const LevelDevT<T>& D, const T* Q, const T* gW, const T* Phi,
                        const DivArgs<T>& a, hipStream_t st) {
-  const size_t lds = L.lds_div();
-  if (L.block == 64) k_div<T, 1, 64><<<L.ntiles, 64, lds, st>>>(D, Q, gW, Phi, a);
-  else if (L.block == 128) k_div<T, 1, 128><<<L.ntiles, 128, lds, st>>>(D, Q, gW, Phi, a);
-  else if (L.max_tile <= PMG_BLOCK) k_div<T, 1, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, gW, Phi, a);
-  else k_div<T, PMG_NPT, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, lds, st>>>(D, Q, gW, Phi, a);
+  for (const TileClass& c : L.tcls) {
+    if (!c.count) continue;
+    const LevelDevT<T> Dc = class_dev(D, c);
+    DivArgs<T> ac = a;
+    if (ac.norm) ac.norm += c.first;
+    const size_t lds = L.lds_div(c);
+    if (c.block == 64) k_div<T, 1, 64><<<c.count, 64, lds, st>>>(Dc, Q, gW, Phi, ac);
+    else if (c.block == 128) k_div<T, 1, 128><<<c.count, 128, lds, st>>>(Dc, Q, gW, Phi, ac);
+    else if (c.npt == 1) k_div<T, 1, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, gW, Phi, ac);
+    else k_div<T, PMG_NPT, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, gW, Phi, ac);
+  }
 }
 
 template <class T>
 static void launch_dt(const Level& L, const LevelDevT<T>& D, const T* Q, unsigned long long* out, hipStream_t st) {
-  if (L.block == 64) k_dt<T, 64><<<L.ntiles, 64, 0, st>>>(D, Q, L.d_hfac, out);
-  else if (L.block == 128) k_dt<T, 128><<<L.ntiles, 128, 0, st>>>(D, Q, L.d_hfac, out);
-  else k_dt<T, PMG_BLOCK><<<L.ntiles, PMG_BLOCK, 0, st>>>(D, Q, L.d_hfac, out);
+  for (const TileClass& c : L.tcls) {
+    if (!c.count) continue;
+    const LevelDevT<T> Dc = class_dev(D, c);
+    if (c.block == 64) k_dt<T, 64><<<c.count, 64, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
+    else if (c.block == 128) k_dt<T, 128><<<c.count, 128, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
+    else k_dt<T, PMG_BLOCK><<<c.count, PMG_BLOCK, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
+  }
 }
 
 // A(Q) through the stages: q traces, interface state + Roe flux, gradient (+ gradient traces), viscous
@@ -891,7 +964,8 @@ static void reduce_tiles(const pmg_solver_s* s, const Level& L, int slot, bool t
   const double init = take_max ? 0.0 : INFINITY;
   unsigned long long bits;
   memcpy(&bits, &init, sizeof(bits));
-  k_tile_reduce<<<s->nprob, 256, 0, st>>>(s->d_part, L.d_ptile, act, take_max ? 1 : 0, bits, slot_ptr(s, slot));
+  k_tile_reduce<<<s->nprob, 256, 0, st>>>(s->d_part, L.d_ptile, (int)L.tcls.size(), s->nprob, act,
+                                           take_max ? 1 : 0, bits, slot_ptr(s, slot));
 }
 
 template <class T>
@@ -1030,9 +1104,11 @@ static std::string level_key(const pmg_solver_s* s, const Level& L) {
 static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
   traces_stale(s);
   std::string key = level_key(s, L);
+  // cached choice: target | split << 16
   auto it = s->ctx->tile_cache.find(key);
   if (it != s->ctx->tile_cache.end()) {
-    if (it->second != L.tile_target) build_tiles(s, L, it->second);
+    const int tg = it->second & 0xffff, sp = it->second >> 16;
+    if (tg != L.tile_target || sp != L.tile_split) build_tiles(s, L, tg, sp);
     return;
   }
   DevArena tmp;
@@ -1045,10 +1121,16 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
   HIPCHECK(hipEventCreate(&e1));
   uint32_t mask = s->prof->mask;
   s->prof->mask = 0;
-  int best = L.tile_target;
+  int best = L.tile_target, best_split = L.tile_split;
   float best_t = 1e30f;
-  for (int target : {64, 128, 256, 512}) {
-    build_tiles(s, L, target);
+  for (int cand = 0; cand < 8; cand++) {
+    const int target = 64 << (cand >> 1), split = cand & 1;
+    build_tiles(s, L, target, split);
+    if (split && L.tcls.size() > 1) {
+      int used = 0;
+      for (const TileClass& c : L.tcls) used += c.count > 0;
+      if (used < 2) continue;  // one class: the same launches as without the split
+    }
     residual_any(s, L, Q, nullptr, R, false, -1, st);  // warm
     HIPCHECK(hipEventRecord(e0, st));
     for (int r = 0; r < 3; r++) residual_any(s, L, Q, nullptr, R, false, -1, st);
@@ -1059,14 +1141,15 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
     if (t < best_t) {
       best_t = t;
       best = target;
+      best_split = split;
     }
   }
   s->prof->mask = mask;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   traces_stale(s);  // the timing state is freed
-  if (best != L.tile_target) build_tiles(s, L, best);
-  s->ctx->tile_cache[key] = best;
+  if (best != L.tile_target || best_split != L.tile_split) build_tiles(s, L, best, best_split);
+  s->ctx->tile_cache[key] = best | best_split << 16;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1847,12 +1930,29 @@ pmg_status pmg_autotune(pmg_solver s, void* stream) {
   });
 }
 
-pmg_status pmg_level_tiles(pmg_solver s, int hierarchy, int level, int32_t* tile_target) {
+pmg_status pmg_set_tiles(pmg_solver s, int hierarchy, int level, int tile_target, int split) {
+  return guard([&] {
+    REQUIRE(s, "NULL solver");
+    REQUIRE(tile_target == 64 || tile_target == 128 || tile_target == 256 || tile_target == 512,
+            "tile_target must be 64, 128, 256 or 512");
+    REQUIRE(split == 0 || split == 1, "split must be 0 or 1");
+    Hier& H = pick_hier(s, hierarchy);
+    REQUIRE(level >= 0 && level < (int)H.lv.size(), "level out of range");
+    HIPCHECK(hipDeviceSynchronize());  // launches in flight read the tile arrays that are replaced
+    traces_stale(s);
+    build_tiles(s, *H.lv[level], tile_target, split);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);  // tiles changed: recapture
+    s->graphs.clear();
+  });
+}
+
+pmg_status pmg_level_tiles(pmg_solver s, int hierarchy, int level, int32_t* tile_target, int32_t* split) {
   return guard([&] {
     REQUIRE(s && tile_target, "NULL argument");
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 0 && level < (int)H.lv.size(), "level out of range");
     *tile_target = H.lv[level]->tile_target;
+    if (split) *split = H.lv[level]->tile_split;
   });
 }
 
@@ -1891,21 +1991,29 @@ static void cycle_once(pmg_solver_s* s, Hier& H, int kind, double* Q, const doub
 }
 
 // Stopping and precision bookkeeping of one problem: FP32 coarse levels are kept while the residual keeps
-// reaching new minima; after 'patience' cycles without one (the FP32 round-off floor of the coarse
-// correction) the problem continues with FP64 coarse levels.  Cycles count as stalled only once the residual
-// has fallen below its first value: a start-up transient that raises the residual is no round-off floor.
+// reaching new minima; after 'patience' stalled cycles (the FP32 round-off floor of the coarse correction)
+// the problem continues with FP64 coarse levels.  At a round-off floor the residual hovers at its minimum,
+// up one cycle and down the next; a start-up transient raises it cycle after cycle.  So a cycle counts as
+// stalled only when it reaches no new minimum, the residual has fallen below its first value, stays within
+// twice its best value and did not rise over the cycle.  A cycle the divergence guard rolled back is no
+// evidence either way and restarts the count.
 struct MixedState {
   int f32 = 0, stall = 0;
-  double best = INFINITY, first = -1.0;
+  double best = INFINITY, first = -1.0, prev = INFINITY;
   void update(double r, int patience) {
     if (!f32) return;
     if (first < 0.0) first = r;
     if (r < best) {
       best = r;
       stall = 0;
-    } else if (best < first && ++stall >= patience) {
+    } else if (best < first && r <= 2.0 * best && r <= prev && ++stall >= patience) {
       f32 = 0;
     }
+    prev = r;
+  }
+  void rolled_back() {
+    stall = 0;
+    prev = INFINITY;
   }
 };
 
@@ -1921,9 +2029,10 @@ struct DivGuard {
   hipStream_t st;
   std::vector<double> r_ok, r_start;  // residuals at the last accepted check and at the start of the call
   std::vector<int> fails;             // per problem: failures since its last accepted check
+  std::vector<int> rolled;            // per problem: restored at the last check
   bool first = true;
   DivGuard(pmg_solver_s* s_, hipStream_t st_)
-      : s(s_), st(st_), r_ok(s_->nprob, 0.0), r_start(s_->nprob, 0.0), fails(s_->nprob, 0) {
+      : s(s_), st(st_), r_ok(s_->nprob, 0.0), r_start(s_->nprob, 0.0), fails(s_->nprob, 0), rolled(s_->nprob, 0) {
     if (s->mg.guard > 0 && !s->d_Qbak) {
       s->d_Qbak = s->arena.alloc<double>(5 * (size_t)s->top->nn);
       s->d_Qstart = s->arena.alloc<double>(5 * (size_t)s->top->nn);
@@ -1941,6 +2050,7 @@ struct DivGuard {
   // accepted state).
   std::vector<int> check(std::vector<double>& r, const std::vector<int>& advanced, double* Q) {
     std::vector<int> failed;
+    std::fill(rolled.begin(), rolled.end(), 0);
     if (s->mg.guard <= 0) return failed;
     const Level& T = *s->top;
     bool restored = false;
@@ -1951,6 +2061,7 @@ struct DivGuard {
         continue;
       }
       restored = true;
+      rolled[p] = 1;
       if (s->halvings[p] >= s->mg.guard) {
         restore(p, s->d_Qbak, Q);
         r[p] = r_ok[p];
@@ -2025,7 +2136,8 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
       s->history.push_back(r);
       if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
       if (r < tol || cycles >= max_cycles) break;
-      ms.update(r, patience);
+      if (dg.rolled[0]) ms.rolled_back();
+      else ms.update(r, patience);
       if (s->mg.tuning) {
         // residual-based tuning reads norms inside the cycle: eager launches
         Hier& Hc = ms.f32 ? s->iso : iso_f64(s);
@@ -2070,7 +2182,8 @@ pmg_status pmg_batch_solve(pmg_solver s, double* Q_dev, const double* S_dev, dou
         if (dead[p]) active[p] = 0;
         if (r[p] != r[p]) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual in problem " + std::to_string(p));
         if (active[p] && (r[p] < tol || cyc[p] >= max_cycles)) active[p] = 0;  // converged problems freeze
-        if (active[p]) ms[p].update(r[p], patience);
+        if (active[p] && dg.rolled[p]) ms[p].rolled_back();
+        else if (active[p]) ms[p].update(r[p], patience);
         a32[p] = active[p] && ms[p].f32;
         a64[p] = active[p] && !ms[p].f32;
         n32 += a32[p];

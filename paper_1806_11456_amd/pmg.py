@@ -27,7 +27,7 @@ EXPORTS = ["pmg_last_error", "pmg_ctx_create", "pmg_ctx_destroy", "pmg_mesh_crea
            "pmg_remap_state", "pmg_adapt_multistage", "pmg_wall_force", "pmg_wall_force_noalloc",
            "pmg_force_coefficients", "pmg_batch_create",
            "pmg_batch_layout", "pmg_batch_norms", "pmg_batch_solve", "pmg_set_graph", "pmg_autotune",
-           "pmg_level_tiles", "pmg_solve_stats", "pmg_guard_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
+           "pmg_level_tiles", "pmg_set_tiles", "pmg_solve_stats", "pmg_guard_stats", "pmg_footprint", "pmg_device_bytes", "pmg_server_create",
            "pmg_server_submit", "pmg_server_poll", "pmg_server_stats", "pmg_server_destroy", "pmg_tau_nodal",
            "pmg_solve_history", "pmg_cycle_count", "pmg_checkpoint", "pmg_restore"]
 
@@ -129,7 +129,8 @@ def lib():
     L.pmg_batch_solve.argtypes = [P, V, V, C.c_double, C.c_int, I32, D, V]
     L.pmg_set_graph.argtypes = [P, C.c_int]
     L.pmg_autotune.argtypes = [P, V]
-    L.pmg_level_tiles.argtypes = [P, C.c_int, C.c_int, I32]
+    L.pmg_level_tiles.argtypes = [P, C.c_int, C.c_int, I32, I32]
+    L.pmg_set_tiles.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
     L.pmg_solve_stats.argtypes = [P, I32]
     L.pmg_guard_stats.argtypes = [P, I32, D]
     L.pmg_footprint.argtypes = [P, I32, C.POINTER(MGParams), I64, I64, I64]
@@ -520,9 +521,18 @@ class Solver:
         _check(lib().pmg_autotune(self.h, _stream()))
 
     def level_tiles(self, hierarchy: int, level: int) -> int:
-        t = C.c_int32()
-        _check(lib().pmg_level_tiles(self.h, hierarchy, level, C.byref(t)))
-        return int(t.value)
+        """The level's element-tile node target (64, 128, 256 or 512)."""
+        return self.level_tile_choice(hierarchy, level)[0]
+
+    def set_tiles(self, hierarchy: int, level: int, target: int, split: bool = False):
+        """Rebuild one level's element tiles for a node target and launch split (pmg_set_tiles)."""
+        _check(lib().pmg_set_tiles(self.h, hierarchy, level, int(target), int(bool(split))))
+
+    def level_tile_choice(self, hierarchy: int, level: int):
+        """(node target, split): split is True when the level's tiles are launched per size class."""
+        t, sp = C.c_int32(), C.c_int32()
+        _check(lib().pmg_level_tiles(self.h, hierarchy, level, C.byref(t), C.byref(sp)))
+        return int(t.value), bool(sp.value)
 
 
 class Batch(Solver):
