@@ -329,8 +329,9 @@ def plate_line(args) -> dict:
 def serve_bench(args) -> dict:
     """Served stream (configuration 5 recipe, reduced sizes): Poisson arrivals at 20/s of steady-solve
     requests on random stretched boxes with a wall, solved to ||r||_inf < 1e-9 by the continuous-batching
-    server; baseline: the same list solved one after another with pmg_solve (plain FP64) on the same GPU,
-    queued first come, first served at the same arrival times.  Both include solver construction."""
+    server, per-request solvers on several streams and union solvers (batched); baseline: the same list
+    solved one after another with pmg_solve (plain FP64) on the same GPU, queued first come, first served at
+    the same arrival times.  All include solver construction."""
     import numpy as np
     import torch
 
@@ -343,62 +344,78 @@ def serve_bench(args) -> dict:
     mg = pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4, precision=args.serve_precision)
     meshes = [pmg.Mesh(ctx, w.mesh) for _, w, _ in reqs]
     max_cycles = 20000
+    pct = lambda x, q: float(np.percentile(x, q))
 
-    # served
-    states = [torch.tensor(w.Q, dtype=torch.float64, device="cuda") for _, w, _ in reqs]
-    torch.cuda.synchronize()
-    sv = pmg.Server(ctx, int(args.serve_budget_gib * 2 ** 30), n_streams=args.serve_streams, use_graph=True)
-    t0 = time.perf_counter()
-    tickets = []
-    for (arr, w, tol), m, Q in zip(reqs, meshes, states):
-        dt = t0 + arr - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
-        tickets.append(sv.submit(m, w.orders, w.phys, mg, Q, tol=tol, max_cycles=max_cycles))
-    done = {}
-    last = t0
-    while len(done) < len(tickets):
-        for t in tickets:
-            if t not in done:
-                r = sv.poll(t)
-                if r is not None:
-                    done[t] = r
-                    last = time.perf_counter()
-                    print(f"served {len(done)}/{len(tickets)}: {r}", file=sys.stderr, flush=True)
-        time.sleep(0.001)
-    stats = sv.stats()
-    sv.close()
-    served = [done[t] for t in tickets]
-    lat = np.array([r["latency_s"] for r in served])
-    ok = sum(r["status"] == 0 for r in served)
+    def served_run(batched: bool) -> dict:
+        states = [torch.tensor(w.Q, dtype=torch.float64, device="cuda") for _, w, _ in reqs]
+        torch.cuda.synchronize()
+        sv = pmg.Server(ctx, int(args.serve_budget_gib * 2 ** 30), n_streams=args.serve_streams, use_graph=True,
+                        batched=batched)
+        t0 = time.perf_counter()
+        tickets = []
+        for (arr, w, tol), m, Q in zip(reqs, meshes, states):
+            dt = t0 + arr - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(sv.submit(m, w.orders, w.phys, mg, Q, tol=tol, max_cycles=max_cycles))
+        done = {}
+        last = t0
+        while len(done) < len(tickets):
+            for t in tickets:
+                if t not in done:
+                    r = sv.poll(t)
+                    if r is not None:
+                        done[t] = r
+                        last = time.perf_counter()
+                        print(f"served{' batched' if batched else ''} {len(done)}/{len(tickets)}: {r}",
+                              file=sys.stderr, flush=True)
+            time.sleep(0.001)
+        stats = sv.stats()
+        sv.close()
+        served = [done[t] for t in tickets]
+        lat = np.array([r["latency_s"] for r in served])
+        return {"p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "solves_per_s": len(reqs) / (last - t0),
+                "makespan_s": last - t0, "converged": int(sum(r["status"] == 0 for r in served)),
+                "cycles_total": int(sum(r["cycles"] for r in served)), "max_resident": stats["max_resident"],
+                "peak_bytes": stats["peak_bytes"], "iterations": stats["iterations"]}
+
+    modes = [m for m in args.serve_modes.split(",") if m]
+    out_served = {}
+    for m in modes:
+        assert m in ("per-request", "batched"), m
+        out_served[m] = served_run(m == "batched")
 
     # baseline: sequential plain FP64 solves
-    solve_t = []
-    base_ok = 0
-    for (arr, w, tol), m in zip(reqs, meshes):
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        s = pmg.Solver(ctx, m, w.orders, w.phys, pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4))
-        s.set_graph(True)
-        Q = s.tensor(w.Q)
-        cyc, r = s.solve(Q, None, tol=tol, max_cycles=max_cycles, raise_not_converged=False)
-        torch.cuda.synchronize()
-        solve_t.append(time.perf_counter() - a)
-        base_ok += r < tol
-        print(f"sequential {len(solve_t)}/{len(reqs)}: {cyc} cycles, {solve_t[-1]:.2f} s", file=sys.stderr,
-              flush=True)
-        del s, Q
-    end = 0.0
-    blat = []
-    for (arr, _, _), d in zip(reqs, solve_t):
-        start = max(arr, end)
-        end = start + d
-        blat.append(end - arr)
-    blat = np.array(blat)
-    pct = lambda x, q: float(np.percentile(x, q))
+    seq = None
+    if not args.serve_no_sequential:
+        solve_t = []
+        base_ok = 0
+        for (arr, w, tol), m in zip(reqs, meshes):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            s = pmg.Solver(ctx, m, w.orders, w.phys, pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4))
+            s.set_graph(True)
+            Q = s.tensor(w.Q)
+            cyc, r = s.solve(Q, None, tol=tol, max_cycles=max_cycles, raise_not_converged=False)
+            torch.cuda.synchronize()
+            solve_t.append(time.perf_counter() - a)
+            base_ok += r < tol
+            print(f"sequential {len(solve_t)}/{len(reqs)}: {cyc} cycles, {solve_t[-1]:.2f} s", file=sys.stderr,
+                  flush=True)
+            del s, Q
+        end = 0.0
+        blat = []
+        for (arr, _, _), d in zip(reqs, solve_t):
+            start = max(arr, end)
+            end = start + d
+            blat.append(end - arr)
+        blat = np.array(blat)
+        seq = {"p50_s": pct(blat, 50), "p99_s": pct(blat, 99), "solves_per_s": len(reqs) / end, "makespan_s": end,
+               "converged": int(base_ok), "solve_s_mean": float(np.mean(solve_t))}
+    head = out_served[modes[0]]
     return {
         "metric": "p50/p99 latency (arrival to result); solves/s",
-        "value": pct(lat, 50),
+        "value": head["p50_s"],
         "unit": "s",
         "higher_is_better": False,
         "n_gpus": 1,
@@ -409,14 +426,9 @@ def serve_bench(args) -> dict:
                                "field, orders U{1..4} per direction, Mach U[0.1,0.4], Re U[1e3,1e4], tol 1e-9, "
                                "V-cycles beta 2/2/4",
                    "dof_total": int(sum(w.n_nodes for _, w, _ in reqs)), "streams": args.serve_streams,
-                   "hbm_budget_gib": args.serve_budget_gib},
-        "served": {"p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "solves_per_s": len(reqs) / (last - t0),
-                   "makespan_s": last - t0, "converged": ok, "cycles_total": int(sum(r["cycles"] for r in served)),
-                   "max_resident": stats["max_resident"], "peak_bytes": stats["peak_bytes"],
-                   "iterations": stats["iterations"]},
-        "sequential_fp64": {"p50_s": pct(blat, 50), "p99_s": pct(blat, 99), "solves_per_s": len(reqs) / end,
-                            "makespan_s": end, "converged": int(base_ok),
-                            "solve_s_mean": float(np.mean(solve_t))},
+                   "hbm_budget_gib": args.serve_budget_gib, "value_from": modes[0]},
+        "served": out_served,
+        "sequential_fp64": seq,
     }
 
 
@@ -920,6 +932,10 @@ def main() -> int:
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-precision", type=int, default=0)
+    ap.add_argument("--serve-modes", default="per-request,batched",
+                    help="served runs, in order: per-request (a solver per request, several streams), batched "
+                         "(union solvers)")
+    ap.add_argument("--serve-no-sequential", action="store_true")
     ap.add_argument("--solve", action="store_true", help="time to a converged plate solve instead of throughput")
     ap.add_argument("--solve-batch", action="store_true", help="progress of the 64-problem batch toward the tolerance")
     ap.add_argument("--solve-batch-chunk", type=int, default=25)

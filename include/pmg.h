@@ -283,12 +283,21 @@ pmg_status pmg_device_bytes(int64_t* bytes);
  *   resident unfinished request, spread over n_streams HIP streams (captured graphs when use_graph = 1),
  *   then every request's residual norm, then waits once; new arrivals join at the next iteration, converged
  *   or failed requests retire and release their memory.
- * - Each request runs exactly the launch sequence of pmg_solve on its own solver (mixed-precision switch
- *   included), so its result is bitwise the result of solving it alone.
+ * - batched = 0: each request runs exactly the launch sequence of pmg_solve on its own solver (mixed-precision
+ *   switch included), one stream per request in turn.
+ * - batched = 1: resident requests with the same multigrid parameters, node family and maximum order share
+ *   one union solver (as pmg_batch_create) on one stream: each iteration is one batched V-cycle for the members
+ *   on FP32 coarse levels and one for those on FP64 ones (members not advanced skip their tiles), then one
+ *   residual launch with every member's norm.  The union holds the members' states and is rebuilt when its
+ *   membership changes (states copied back to the members and in again); a retiring member's state is
+ *   copied back before it is reported done.
+ * - Either way each request's arithmetic is that of its own solve, so its result is bitwise the result of
+ *   solving it alone.
  * The server's functions may be called from any thread.  Destroying the server stops the worker after its
  * current iteration; requests still resident or queued are abandoned (their state is left as it is).
  */
-pmg_status pmg_server_create(pmg_ctx ctx, int64_t hbm_budget_bytes, int n_streams, int use_graph, pmg_server* out);
+pmg_status pmg_server_create(pmg_ctx ctx, int64_t hbm_budget_bytes, int n_streams, int use_graph, int batched,
+                             pmg_server* out);
 pmg_status pmg_server_submit(pmg_server sv, pmg_mesh mesh, const int32_t* orders, const pmg_physics* phys,
                              const pmg_mg_params* mg, double* Q_dev, double tol, int max_cycles, uint64_t* ticket);
 /* done = 0 while queued or resident.  When done: status (PMG_OK converged, PMG_ERR_NOT_CONVERGED,

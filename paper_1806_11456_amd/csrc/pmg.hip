@@ -2278,6 +2278,7 @@ struct pmg_server_s {
   pmg_ctx ctx = nullptr;
   double budget = 0.0;
   int graph = 1;
+  int batched = 0;
   std::vector<hipStream_t> streams;
   std::mutex mu;
   std::condition_variable cv;
@@ -2403,6 +2404,248 @@ static void server_loop(pmg_server_s* sv) {
   sv->n_resident = 0;
 }
 
+// Batched serving: the resident requests that can share a solver (same multigrid parameters, node family and
+// maximum order) advance together in one union solver (the batch solver of pmg_batch_create) on one stream,
+// one batched V-cycle per iteration for the requests on FP32 coarse levels and one for those on FP64 ones,
+// then one residual launch for every member.  The union holds the members' states; it is rebuilt when its
+// membership changes (each remaining member's state copied out, the new union built, the states copied in)
+// and a retiring member's state is copied back before it is reported done.  Per-problem arithmetic in a union
+// is that of the problem's own solver, so results stay bitwise those of solving each request alone.
+struct ServerGroup {
+  std::string key;
+  std::vector<std::shared_ptr<ServerReq>> reqs;  // members, in union order
+  pmg_solver_s* u = nullptr;
+  double* Qu = nullptr;     // union state [5][nn] (u's arena)
+  std::vector<size_t> off;  // first union node of each member
+  size_t nn = 0;
+  bool dirty = true;
+  hipStream_t st = nullptr;
+};
+
+static std::string server_group_key(const ServerReq& r) {
+  int pmax = 1;
+  for (int v : r.orders) pmax = std::max(pmax, v);
+  const pmg_mg_params& m = r.mg;
+  std::string k = std::to_string(pmax) + ":" + std::to_string(r.phys.node_family);
+  k += ":" + std::to_string(m.beta_pre) + "," + std::to_string(m.beta_post) + "," + std::to_string(m.beta_coarse);
+  k += ":" + std::to_string(m.precision) + "," + std::to_string(m.mixed_patience) + "," + std::to_string(m.n_levels);
+  for (int c : r.caps) k += "," + std::to_string(c);
+  return k;
+}
+
+// member p's range of the union state <-> its own state
+static void group_copy(ServerGroup& g, size_t p, bool to_union) {
+  const ServerReq& r = *g.reqs[p];
+  const size_t n = g.off[p + 1] - g.off[p];  // the member's own node count
+  for (int v = 0; v < 5; v++) {
+    double* a = g.Qu + (size_t)v * g.nn + g.off[p];
+    double* b = r.Q + (size_t)v * n;
+    HIPCHECK(hipMemcpyAsync(to_union ? a : b, to_union ? b : a, n * sizeof(double), hipMemcpyDeviceToDevice, g.st));
+  }
+}
+
+static void group_release(ServerGroup& g) {
+  if (!g.u) return;
+  for (size_t p = 0; p < g.reqs.size(); p++) group_copy(g, p, false);
+  HIPCHECK(hipStreamSynchronize(g.st));
+  delete g.u;
+  g.u = nullptr;
+  g.Qu = nullptr;
+}
+
+static void group_build(pmg_server_s* sv, ServerGroup& g) {
+  std::vector<const pmg_mesh_s*> meshes;
+  std::vector<const int32_t*> orders;
+  std::vector<pmg_physics> phys;
+  for (auto& r : g.reqs) {
+    meshes.push_back(r->mesh);
+    orders.push_back(r->orders.data());
+    phys.push_back(r->phys);
+  }
+  pmg_mg_params mg = g.reqs[0]->mg;
+  mg.level_caps = g.reqs[0]->caps.empty() ? nullptr : g.reqs[0]->caps.data();
+  g.u = create_solver(sv->ctx, meshes, orders, phys.data(), &mg);
+  g.u->use_graph = sv->graph;
+  const Level& T = *g.u->top;
+  g.nn = (size_t)T.nn;
+  g.off.assign(g.reqs.size() + 1, 0);
+  for (size_t p = 0; p <= g.reqs.size(); p++) g.off[p] = (size_t)T.off[g.u->prob_elem[p]];
+  g.Qu = g.u->arena.alloc<double>(5 * g.nn);
+  for (size_t p = 0; p < g.reqs.size(); p++) group_copy(g, p, true);
+  g.dirty = false;
+}
+
+static void server_loop_batched(pmg_server_s* sv) {
+  if (hipSetDevice(sv->ctx->device) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->fatal = "hipSetDevice failed in the server thread";
+    return;
+  }
+  std::vector<ServerGroup> groups;
+  auto n_resident = [&] {
+    size_t n = 0;
+    for (auto& g : groups) n += g.reqs.size();
+    return n;
+  };
+  for (;;) {
+    std::vector<std::shared_ptr<ServerReq>> admit;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      if (n_resident() == 0) sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+      if (sv->stop) break;
+      while (!sv->queue.empty() && sv->used + sv->queue.front()->est <= sv->budget) {
+        auto r = sv->queue.front();
+        sv->queue.pop_front();
+        sv->used += r->est;
+        sv->peak = std::max(sv->peak, sv->used);
+        r->t_admit = sv->now();
+        admit.push_back(r);
+      }
+    }
+    for (auto& r : admit) {
+      const std::string key = server_group_key(*r);
+      ServerGroup* g = nullptr;
+      for (auto& x : groups)
+        if (x.key == key) g = &x;
+      if (!g) {
+        groups.emplace_back();
+        g = &groups.back();
+        g->key = key;
+        g->st = sv->streams[(groups.size() - 1) % sv->streams.size()];
+      }
+      if (g->u) {
+        // the union is rebuilt with the new member: the current members' states go back to them first
+        pmg_status rc = guard([&] { group_release(*g); });
+        if (rc != PMG_OK) {
+          std::lock_guard<std::mutex> lk(sv->mu);
+          sv->fatal = "server: " + g_err;
+        }
+      }
+      r->ms.f32 = r->mg.precision == 1;
+      g->reqs.push_back(r);
+      g->dirty = true;
+    }
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->n_resident = (int)n_resident();
+      sv->max_resident = std::max(sv->max_resident, sv->n_resident);
+      if (!sv->fatal.empty()) break;
+    }
+    for (auto& g : groups) {
+      if (g.reqs.empty()) continue;
+      if (g.dirty) {
+        pmg_status rc = guard([&] { group_build(sv, g); });
+        if (rc != PMG_OK) {
+          // the union could not be built: every member fails with the error
+          for (auto& r : g.reqs) {
+            r->err = g_err;
+            server_retire(sv, r, rc);
+          }
+          g.reqs.clear();
+          g.u = nullptr;
+          continue;
+        }
+      }
+      // one iteration: the decided cycles, then every member's residual norm (the launch sequence of
+      // pmg_batch_solve: problems not advanced skip their tiles)
+      const int n = (int)g.reqs.size();
+      pmg_solver_s* u = g.u;
+      std::vector<int> a32(n, 0), a64(n, 0);
+      int n32 = 0, n64 = 0;
+      for (int p = 0; p < n; p++) {
+        a32[p] = g.reqs[p]->cycle_next && g.reqs[p]->ms.f32;
+        a64[p] = g.reqs[p]->cycle_next && !g.reqs[p]->ms.f32;
+        n32 += a32[p];
+        n64 += a64[p];
+      }
+      std::vector<double> r;
+      pmg_status rc = guard([&] {
+        traces_stale(u);
+        if (n32) {
+          HIPCHECK(hipMemcpyAsync(u->d_act[0], a32.data(), n * sizeof(int), hipMemcpyHostToDevice, g.st));
+          cycle_once(u, u->iso, 0, g.Qu, nullptr, u->d_act[0], g.st);
+        }
+        if (n64) {
+          HIPCHECK(hipMemcpyAsync(u->d_act[1], a64.data(), n * sizeof(int), hipMemcpyHostToDevice, g.st));
+          cycle_once(u, iso_f64(u), u->mg.precision == 1 ? 2 : 0, g.Qu, nullptr, u->d_act[1], g.st);
+        }
+        residual(u, *u->top, (const double*)g.Qu, (const double*)nullptr, u->d_R, false, SLOT_NORM, g.st);
+        r = read_slots(u, SLOT_NORM, g.st);  // waits for the stream
+      });
+      if (rc != PMG_OK) {
+        for (auto& q : g.reqs) {
+          q->err = g_err;
+          q->status = rc;
+        }
+        r.assign(n, (double)NAN);
+      }
+      std::vector<std::shared_ptr<ServerReq>> keep;
+      std::vector<size_t> keep_p;
+      for (int p = 0; p < n; p++) {
+        auto& q = g.reqs[p];
+        if (a32[p] || a64[p]) {
+          q->cycles++;
+          q->fp32 += a32[p];
+        }
+        int status = q->status >= 0 ? q->status : -1;
+        if (status < 0) {
+          q->r = r[p];
+          if (q->r != q->r) {
+            q->err = "non-finite residual";
+            status = PMG_ERR_NONPHYSICAL;
+          } else if (q->r < q->tol) {
+            status = PMG_OK;
+          } else if (q->cycles >= q->max_cycles) {
+            status = PMG_ERR_NOT_CONVERGED;
+          } else {
+            q->ms.update(q->r, q->mg.mixed_patience > 0 ? q->mg.mixed_patience : 4);
+            q->cycle_next = true;
+          }
+        }
+        if (status >= 0) {
+          // the member's state goes back to it before it is reported done
+          pmg_status rc2 = guard([&] {
+            group_copy(g, (size_t)p, false);
+            HIPCHECK(hipStreamSynchronize(g.st));
+          });
+          if (rc2 != PMG_OK && status == PMG_OK) {
+            q->err = g_err;
+            status = rc2;
+          }
+          server_retire(sv, q, status);
+          g.dirty = true;
+        } else {
+          keep.push_back(q);
+          keep_p.push_back((size_t)p);
+        }
+      }
+      if (g.dirty) {
+        // membership changed: the remaining members' states go back to them; the union is rebuilt next time
+        for (size_t i = 0; i < keep.size(); i++) {
+          pmg_status rc3 = guard([&] { group_copy(g, keep_p[i], false); });
+          (void)rc3;
+        }
+        (void)hipStreamSynchronize(g.st);
+        delete g.u;
+        g.u = nullptr;
+        g.Qu = nullptr;
+      }
+      g.reqs.swap(keep);
+    }
+    groups.erase(std::remove_if(groups.begin(), groups.end(), [](const ServerGroup& g) { return g.reqs.empty(); }),
+                 groups.end());
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->iterations++;
+    sv->n_resident = (int)n_resident();
+  }
+  for (auto& g : groups) {
+    (void)guard([&] { group_release(g); });
+    for (auto& r : g.reqs) server_retire(sv, r, PMG_ERR_BUSY);
+  }
+  std::lock_guard<std::mutex> lk(sv->mu);
+  sv->n_resident = 0;
+}
+
 extern "C" {
 
 pmg_status pmg_footprint(pmg_mesh mesh, const int32_t* orders, const pmg_mg_params* mg, int64_t* bytes,
@@ -2424,7 +2667,8 @@ pmg_status pmg_device_bytes(int64_t* bytes) {
   });
 }
 
-pmg_status pmg_server_create(pmg_ctx ctx, int64_t hbm_budget_bytes, int n_streams, int use_graph, pmg_server* out) {
+pmg_status pmg_server_create(pmg_ctx ctx, int64_t hbm_budget_bytes, int n_streams, int use_graph, int batched,
+                             pmg_server* out) {
   return guard([&] {
     REQUIRE(ctx && out, "NULL argument");
     REQUIRE(hbm_budget_bytes > 0, "the HBM budget must be positive");
@@ -2434,13 +2678,16 @@ pmg_status pmg_server_create(pmg_ctx ctx, int64_t hbm_budget_bytes, int n_stream
     sv->ctx = ctx;
     sv->budget = (double)hbm_budget_bytes;
     sv->graph = use_graph ? 1 : 0;
+    REQUIRE(batched == 0 || batched == 1, "batched must be 0 or 1");
+    sv->batched = batched;
     for (int i = 0; i < n_streams; i++) {
       hipStream_t st;
       HIPCHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
       sv->streams.push_back(st);
     }
     pmg_server_s* p = sv.get();
-    sv->worker = std::thread([p] { server_loop(p); });
+    if (batched) sv->worker = std::thread([p] { server_loop_batched(p); });
+    else sv->worker = std::thread([p] { server_loop(p); });
     *out = sv.release();
   });
 }

@@ -135,7 +135,7 @@ def lib():
     L.pmg_guard_stats.argtypes = [P, I32, D]
     L.pmg_footprint.argtypes = [P, I32, C.POINTER(MGParams), I64, I64, I64]
     L.pmg_device_bytes.argtypes = [I64]
-    L.pmg_server_create.argtypes = [P, C.c_int64, C.c_int, C.c_int, pp]
+    L.pmg_server_create.argtypes = [P, C.c_int64, C.c_int, C.c_int, C.c_int, pp]
     L.pmg_server_submit.argtypes = [P, P, I32, C.POINTER(Physics), C.POINTER(MGParams), V, C.c_double, C.c_int,
                                     C.POINTER(C.c_uint64)]
     L.pmg_server_poll.argtypes = [P, C.c_uint64, I32, I32, I32, I32, D, D, D]
@@ -586,11 +586,12 @@ class Server:
     request is queued or resident, then a dict with status, cycles, fp32_cycles, residual, latency_s and
     queue_s (seconds from submission to admission)."""
 
-    def __init__(self, ctx: Context, hbm_budget_bytes: int, n_streams: int = 4, use_graph: bool = True):
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, n_streams: int = 4, use_graph: bool = True,
+                 batched: bool = False):
         self.ctx = ctx
         h = C.c_void_p()
         _check(lib().pmg_server_create(ctx.h, int(hbm_budget_bytes), int(n_streams), int(bool(use_graph)),
-                                       C.byref(h)))
+                                       int(bool(batched)), C.byref(h)))
         self.h = h
         self._alive = {}  # ticket -> (mesh, state): kept alive until the request is done
 

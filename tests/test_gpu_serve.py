@@ -69,14 +69,19 @@ def test_footprint_matches_allocation(ctx, precision):
         del s
 
 
-def test_served_equals_alone(ctx):
+@pytest.mark.parametrize("batched", [False, True])
+def test_served_equals_alone(ctx, batched):
+    """Per-request solvers on several streams, or union solvers of the requests that can share one (rebuilt
+    as requests arrive and retire): the same results as solving each request alone."""
     import torch
     from paper_1806_11456_amd import pmg
     reqs = requests()
     meshes = [pmg.Mesh(ctx, w.mesh) for w, _ in reqs]
     fps = [sum(pmg.footprint(m, w.orders, pmg.MG(**mg))) for m, (w, mg) in zip(meshes, reqs)]
     budget = int(max(fps) * 1.5)  # at most two of these resident at once: the rest queue
-    sv = pmg.Server(ctx, budget, n_streams=3, use_graph=True)
+    if batched:
+        budget = int(sum(fps) * 0.8)  # most resident together: unions of several members, rebuilt on retirements
+    sv = pmg.Server(ctx, budget, n_streams=3, use_graph=True, batched=batched)
     states, tickets = [], []
     tol = 1e-3
     for m, (w, mg) in zip(meshes, reqs):
@@ -110,19 +115,20 @@ def test_served_equals_alone(ctx):
     sv.close()
 
 
-def test_admission(ctx):
+@pytest.mark.parametrize("batched", [False, True])
+def test_admission(ctx, batched):
     import torch
     from paper_1806_11456_amd import pmg
     w, mg = requests()[0]
     mesh = pmg.Mesh(ctx, w.mesh)
     est = sum(pmg.footprint(mesh, w.orders, pmg.MG(**mg)))
-    sv = pmg.Server(ctx, est // 2, n_streams=1)
+    sv = pmg.Server(ctx, est // 2, n_streams=1, batched=batched)
     Q = torch.tensor(w.Q, dtype=torch.float64, device="cuda")
     with pytest.raises(pmg.PmgError) as e:
         sv.submit(mesh, w.orders, w.phys, pmg.MG(**mg), Q, tol=1e-3, max_cycles=5)
     assert e.value.status == 2  # PMG_ERR_OOM
     sv.close()
-    sv = pmg.Server(ctx, int(est * 1.2), n_streams=2)
+    sv = pmg.Server(ctx, int(est * 1.2), n_streams=2, batched=batched)
     Qs = [torch.tensor(w.Q, dtype=torch.float64, device="cuda") for _ in range(3)]
     ts = [sv.submit(mesh, w.orders, w.phys, pmg.MG(**mg), q, tol=1e-30, max_cycles=3) for q in Qs]
     res = wait(sv, ts)
@@ -131,4 +137,34 @@ def test_admission(ctx):
     assert res[ts[2]]["queue_s"] >= res[ts[0]]["queue_s"]
     for q in Qs[1:]:
         assert torch.equal(q, Qs[0])
+    sv.close()
+
+
+def test_batched_server_shares_unions(ctx):
+    """Requests of equal maximum order and parameters resident together run in one union solver: with all of
+    them admitted at once, one iteration advances every one, and each result is its solve alone."""
+    import torch
+    from paper_1806_11456_amd import pmg
+    ws = I.config_batch(n=4, kmin=20, kmax=40, seed=5)
+    meshes = [pmg.Mesh(ctx, w.mesh) for w in ws]
+    mg = dict(MG, precision=1, mixed_patience=2)
+    fps = [sum(pmg.footprint(m, w.orders, pmg.MG(**mg))) for m, w in zip(meshes, ws)]
+    sv = pmg.Server(ctx, int(sum(fps) * 1.1), n_streams=1, use_graph=True, batched=True)
+    Qs = [torch.tensor(w.Q, dtype=torch.float64, device="cuda") for w in ws]
+    maxc = [6, 9, 12, 15]
+    ts = [sv.submit(m, w.orders, w.phys, pmg.MG(**mg), q, tol=1e-30, max_cycles=c)
+          for m, w, q, c in zip(meshes, ws, Qs, maxc)]
+    res = wait(sv, ts)
+    st = sv.stats()
+    print("server stats", st, [res[t]["cycles"] for t in ts])
+    assert st["completed"] == 4
+    for i, (m, w) in enumerate(zip(meshes, ws)):
+        s = pmg.Solver(ctx, m, w.orders, w.phys, pmg.MG(**mg))
+        Q = s.tensor(w.Q)
+        cyc, r = s.solve(Q, None, tol=1e-30, max_cycles=maxc[i], raise_not_converged=False)
+        got = res[ts[i]]
+        assert got["status"] == 5 and got["cycles"] == cyc == maxc[i], i
+        assert got["fp32_cycles"] == int(s.fp32_cycles()[0]), i
+        assert got["residual"] == r, i
+        assert np.array_equal(np_(Qs[i]), np_(Q)), i
     sv.close()
