@@ -182,12 +182,13 @@ def timed(step, steps: int, warmup: int) -> float:
 
 
 def tile_desc(s):
-    """The autotuned element tiles of each level, finest first: node target, '+split' when the level's tiles
-    are launched per size class."""
+    """The autotuned element tiles of each level, finest first: node target, and which kernels launch once
+    per tile-size class."""
     out = []
     for l in reversed(range(s.level_info(-1))):  # level 0 is the coarsest
         t, sp = s.level_tile_choice(-1, l)
-        out.append(f"{t}{'+split' if sp else ''}")
+        per = [k for k, bit in (("grad", 1), ("div", 2)) if sp & bit]
+        out.append(f"{t}" + (f" split({','.join(per)})" if per else ""))
     return "autotuned per level, finest first: " + ", ".join(out)
 
 

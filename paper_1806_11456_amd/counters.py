@@ -66,13 +66,15 @@ def _base(name: str) -> str:
 
 
 def _last_residuals(rows, R):
-    """Rows of the dispatches of the last R fine-level residuals (each ends with one k_div dispatch)."""
+    """Rows of the dispatches of the last R fine-level residuals.  Each residual ends with its divergence
+    launches (one per launch class of the level's tiles, back to back)."""
     key = (lambda r: int(r["Dispatch_Id"])) if rows and "Dispatch_Id" in rows[0] else None
     order = sorted(range(len(rows)), key=(lambda i: key(rows[i])) if key else (lambda i: i))
-    divs = [i for i in order if _base(rows[i]["Kernel_Name"]) == "k_div"]
-    if len(divs) < R + 1:
-        raise SystemExit(f"fewer than {R + 1} k_div dispatches")
-    start = order.index(divs[-R - 1]) + 1
+    is_div = [_base(rows[i]["Kernel_Name"]) == "k_div" for i in order]
+    ends = [p for p in range(len(order)) if is_div[p] and (p + 1 == len(order) or not is_div[p + 1])]
+    if len(ends) < R + 1:
+        raise SystemExit(f"fewer than {R + 1} residuals")
+    start = ends[-R - 1] + 1
     return [rows[i] for i in order[start:] if _base(rows[i]["Kernel_Name"]) in RESIDUAL_KERNELS]
 
 

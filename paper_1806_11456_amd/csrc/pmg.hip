@@ -176,9 +176,11 @@ struct Level {
   int nf1tiles = 0;                        // face tiles of p-nonconforming interfaces (mortar passes)
   int nfctiles = 0;                        // face tiles of conforming interfaces and boundaries
   int64_t nfl_conf = 0, nfl_bnd = 0, nfl_nc = 0;  // face nodes on conforming / boundary / mortar faces
-  // launch ranges of the element tiles: one holding every tile, or (tile_split) one per block size, the tiles
-  // ordered by class and, within a class, by problem
+  // launch ranges of the element tiles: 'all' holds every tile; with tile_split != 0 the tiles are ordered by
+  // size class (tcls, one per block size) and, within a class, by problem, and the gradient (bit 0) and the
+  // divergence (bit 1) launch once per class; the other kernels always launch once over every tile
   std::vector<TileClass> tcls;
+  TileClass all;
   int tile_split = 0;
   DevArena arena;
   DevArena tile_arena;  // element tiles (rebuilt by the autotuner)
@@ -369,9 +371,10 @@ static unsigned long long* slot_ptr(const pmg_solver_s* s, int slot) { return s-
 // Level construction (Sec. 2 geometry; tiles and faces)
 // ------------------------------------------------------------------------------------------------
 // Element tiles: elements bucketed by (problem, order triple), packed to about 'target' nodes (one element
-// when larger), so every tile has one order triple and one problem.  'split': the tiles are launched in
-// classes by size (at most 64, 128, 256 nodes, larger), each with its own block size and LDS, so that a small
-// tile does not hold the idle lanes of the level's largest block; otherwise every tile is in one launch.
+// when larger), so every tile has one order triple and one problem.  'split' (bit 0 the gradient, bit 1 the
+// divergence): that kernel is launched per class of tiles by size (at most 64, 128, 256 nodes, larger), each
+// with its own block size and LDS, so that a small tile does not hold the idle lanes of the level's largest
+// block; otherwise it is one launch over every tile.
 static void build_tiles(const pmg_solver_s* s, Level& L, int target, int split = 0) {
   std::map<std::pair<int, int>, std::vector<int>> buckets;
   for (int e = 0; e < L.K; e++)
@@ -408,7 +411,7 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target, int split =
           "element tile too large for the device's LDS");
   // launch classes; a stable reorder by class keeps each class's tiles grouped by problem
   auto block_of = [](int nodes) { return nodes <= 64 ? 0 : (nodes <= 128 ? 1 : (nodes <= PMG_BLOCK ? 2 : 3)); };
-  const int ncls = split ? 4 : 1;
+  const int ncls = split ? 4 : 1;  // tiles ordered by class whenever a kernel launches per class
   std::vector<int> tcl(tiles.size(), 0);
   if (split)
     for (size_t t = 0; t < tiles.size(); t++) tcl[t] = block_of(tiles[t].w);
@@ -476,6 +479,16 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target, int split =
   L.tile_target = target;
   L.tile_split = split;
   L.tcls = cls;
+  TileClass A;
+  A.first = 0;
+  A.count = (int)tiles.size();
+  A.max_tile = max_tile;
+  A.grad_words = grad_words;
+  A.div_words = div_words;
+  const int ba = block_of(max_tile);
+  A.block = ba == 0 ? 64 : (ba == 1 ? 128 : PMG_BLOCK);
+  A.npt = ba == 3 ? PMG_NPT : 1;
+  L.all = A;
   L.dev.tiles = L.dev32.tiles = L.d_tiles;
   L.dev.elist = L.dev32.elist = L.d_elist;
   L.dev.eoff = L.dev32.eoff = L.d_eoff;
@@ -806,9 +819,15 @@ static LevelDevT<T> class_dev(const LevelDevT<T>& D, const TileClass& c) {
   return Dc;
 }
 
+// The launch ranges of one kernel: the size classes when its bit of the level's split is set, else all tiles.
+static std::vector<TileClass> launch_ranges(const Level& L, int bit) {
+  if (L.tile_split & bit) return L.tcls;
+  return std::vector<TileClass>(1, L.all);
+}
+
 template <class T>
 static void launch_trace(const Level& L, const LevelDevT<T>& D, const T* Q, T* qf, hipStream_t st) {
-  for (const TileClass& c : L.tcls) {
+  for (const TileClass& c : launch_ranges(L, 0)) {
     if (!c.count) continue;
     const LevelDevT<T> Dc = class_dev(D, c);
     const size_t lds = L.lds_trace(c);
@@ -821,7 +840,7 @@ static void launch_trace(const Level& L, const LevelDevT<T>& D, const T* Q, T* q
 template <class T>
 static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const T* qf, const T* Ws, int isolated,
                         T* gW, T* gf, T* fvn, T* phi, hipStream_t st) {
-  for (const TileClass& c : L.tcls) {
+  for (const TileClass& c : launch_ranges(L, 1)) {
     if (!c.count) continue;
     const LevelDevT<T> Dc = class_dev(D, c);
     const size_t lds = L.lds_grad(c);
@@ -837,7 +856,7 @@ static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const
 template <class T>
 static void launch_div(const Level& L, const LevelDevT<T>& D, const T* Q, const T* gW, const T* Phi,
                        const DivArgs<T>& a, hipStream_t st) {
-  for (const TileClass& c : L.tcls) {
+  for (const TileClass& c : launch_ranges(L, 2)) {
     if (!c.count) continue;
     const LevelDevT<T> Dc = class_dev(D, c);
     DivArgs<T> ac = a;
@@ -852,7 +871,7 @@ static void launch_div(const Level& L, const LevelDevT<T>& D, const T* Q, const 
 
 template <class T>
 static void launch_dt(const Level& L, const LevelDevT<T>& D, const T* Q, unsigned long long* out, hipStream_t st) {
-  for (const TileClass& c : L.tcls) {
+  for (const TileClass& c : launch_ranges(L, 0)) {
     if (!c.count) continue;
     const LevelDevT<T> Dc = class_dev(D, c);
     if (c.block == 64) k_dt<T, 64><<<c.count, 64, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
@@ -1123,21 +1142,29 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
   s->prof->mask = 0;
   int best = L.tile_target, best_split = L.tile_split;
   float best_t = 1e30f;
-  for (int cand = 0; cand < 8; cand++) {
-    const int target = 64 << (cand >> 1), split = cand & 1;
+  for (int cand = 0; cand < 16; cand++) {
+    const int target = 64 << (cand >> 2), split = cand & 3;
     build_tiles(s, L, target, split);
-    if (split && L.tcls.size() > 1) {
+    if (split) {
       int used = 0;
       for (const TileClass& c : L.tcls) used += c.count > 0;
       if (used < 2) continue;  // one class: the same launches as without the split
     }
-    residual_any(s, L, Q, nullptr, R, false, -1, st);  // warm
+    // warm-up, then enough residuals for about 4 ms of timing (at least 3, at most 64)
     HIPCHECK(hipEventRecord(e0, st));
-    for (int r = 0; r < 3; r++) residual_any(s, L, Q, nullptr, R, false, -1, st);
+    residual_any(s, L, Q, nullptr, R, false, -1, st);
+    HIPCHECK(hipEventRecord(e1, st));
+    HIPCHECK(hipEventSynchronize(e1));
+    float t1 = 0.f;
+    HIPCHECK(hipEventElapsedTime(&t1, e0, e1));
+    const int reps = std::max(3, std::min(64, (int)(4.0f / std::max(t1, 1e-3f))));
+    HIPCHECK(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; r++) residual_any(s, L, Q, nullptr, R, false, -1, st);
     HIPCHECK(hipEventRecord(e1, st));
     HIPCHECK(hipEventSynchronize(e1));
     float t = 0.f;
     HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+    t /= (float)reps;
     if (t < best_t) {
       best_t = t;
       best = target;
@@ -1935,7 +1962,7 @@ pmg_status pmg_set_tiles(pmg_solver s, int hierarchy, int level, int tile_target
     REQUIRE(s, "NULL solver");
     REQUIRE(tile_target == 64 || tile_target == 128 || tile_target == 256 || tile_target == 512,
             "tile_target must be 64, 128, 256 or 512");
-    REQUIRE(split == 0 || split == 1, "split must be 0 or 1");
+    REQUIRE(split >= 0 && split <= 3, "split must be 0..3");
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 0 && level < (int)H.lv.size(), "level out of range");
     HIPCHECK(hipDeviceSynchronize());  // launches in flight read the tile arrays that are replaced

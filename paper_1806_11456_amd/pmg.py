@@ -524,15 +524,16 @@ class Solver:
         """The level's element-tile node target (64, 128, 256 or 512)."""
         return self.level_tile_choice(hierarchy, level)[0]
 
-    def set_tiles(self, hierarchy: int, level: int, target: int, split: bool = False):
-        """Rebuild one level's element tiles for a node target and launch split (pmg_set_tiles)."""
-        _check(lib().pmg_set_tiles(self.h, hierarchy, level, int(target), int(bool(split))))
+    def set_tiles(self, hierarchy: int, level: int, target: int, split: int = 0):
+        """Rebuild one level's element tiles for a node target and launch split bits (bit 0 the gradient,
+        bit 1 the divergence launched per tile-size class; pmg_set_tiles)."""
+        _check(lib().pmg_set_tiles(self.h, hierarchy, level, int(target), int(split)))
 
     def level_tile_choice(self, hierarchy: int, level: int):
-        """(node target, split): split is True when the level's tiles are launched per size class."""
+        """(node target, split bits): bit 0 / bit 1 set when the gradient / divergence launches per size class."""
         t, sp = C.c_int32(), C.c_int32()
         _check(lib().pmg_level_tiles(self.h, hierarchy, level, C.byref(t), C.byref(sp)))
-        return int(t.value), bool(sp.value)
+        return int(t.value), int(sp.value)
 
 
 class Batch(Solver):

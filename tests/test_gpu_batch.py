@@ -159,7 +159,7 @@ def _set_all_tiles(s, target, split, hierarchies=(-1,)):
             assert s.level_tile_choice(h, l) == (target, split)
 
 
-TILE_CHOICES = [(t, sp) for t in (64, 128, 256, 512) for sp in (False, True)]
+TILE_CHOICES = [(t, sp) for t in (64, 128, 256, 512) for sp in range(4)]
 
 
 def test_tile_choices_bitwise_batch(ctx, problems):
