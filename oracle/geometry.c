@@ -73,7 +73,12 @@ or_level* or_level_create(const or_problem* P, const int32_t* ord) {
     double* dV = (double*)malloc(sizeof(double) * npe);
     const double* g = P->gnodes + (int64_t)e * (M1 + 1) * (M2 + 1) * (M3 + 1) * 3;
 
-    /* X at the solution nodes: the degree-M mapping on equispaced reference nodes */
+    /* X at the solution nodes: the degree-M mapping on equispaced reference nodes.  The Lagrange weights sum
+     * to one, so the mapping of the nodes taken relative to the element's first mapping node x0 is X - x0
+     * exactly; evaluated that way, X - x0 and its derivatives carry round-off relative to the element's size,
+     * not to its distance from the origin (which on a thin wall cell far from the origin is larger by the
+     * ratio of the two). */
+    const double x0[3] = {g[0], g[1], g[2]};
     for (int k = 0; k < n[2]; k++)
       for (int j = 0; j < n[1]; j++)
         for (int i = 0; i < n[0]; i++) {
@@ -85,29 +90,26 @@ or_level* or_level_create(const or_problem* P, const int32_t* ord) {
               for (int c1 = 0; c1 <= M1; c1++) {
                 double l1 = or_lagrange(M1 + 1, eq[0], c1, b[0]->x[i]);
                 const double* gp = g + (((int64_t)c3 * (M2 + 1) + c2) * (M1 + 1) + c1) * 3;
-                for (int c = 0; c < 3; c++) x[c] += l1 * l2 * l3 * gp[c];
+                for (int c = 0; c < 3; c++) x[c] += l1 * l2 * l3 * (gp[c] - x0[c]);
               }
             }
           }
           for (int c = 0; c < 3; c++) X[c * npe + vidx(n, i, j, k)] = x[c];
         }
-    /* covariant derivatives of I^N X */
+    /* covariant derivatives of I^N X (from X - x0: the derivative of a constant vanishes) */
     for (int m = 0; m < 3; m++)
       for (int d = 0; d < 3; d++) deriv(b, n, d, X + m * npe, dX + (m * 3 + d) * npe);
 
     double* Ja = (double*)calloc(9 * npe, sizeof(double)); /* Ja[(i*3 + comp)*npe + node] */
     /* The curl form is unchanged when X is shifted by a constant (the discrete curl of a discrete gradient
-     * vanishes), so it is evaluated on coordinates relative to the element's first mapping node: the
-     * products then carry round-off relative to the element size, not to the distance from the origin. */
-    const double x0[3] = {g[0], g[1], g[2]};
+     * vanishes), so it is evaluated on X - x0 as held in X. */
     /* invariant curl form, component n_ of every J a^i */
     for (int nc = 0; nc < 3; nc++) {
       int mc = (nc + 1) % 3, lc = (nc + 2) % 3;
       /* V_c = X_l dX_m/dxi_c - X_m dX_l/dxi_c at the nodes (I^N of the product) */
       for (int c = 0; c < 3; c++)
         for (int p = 0; p < npe; p++)
-          V[c * npe + p] = (X[lc * npe + p] - x0[lc]) * dX[(mc * 3 + c) * npe + p] -
-                           (X[mc * npe + p] - x0[mc]) * dX[(lc * 3 + c) * npe + p];
+          V[c * npe + p] = X[lc * npe + p] * dX[(mc * 3 + c) * npe + p] - X[mc * npe + p] * dX[(lc * 3 + c) * npe + p];
       /* (curl V)_1 = d2 V3 - d3 V2; (curl V)_2 = d3 V1 - d1 V3; (curl V)_3 = d1 V2 - d2 V1 */
       for (int i = 0; i < 3; i++) {
         int a = (i + 1) % 3, bb = (i + 2) % 3;
@@ -127,7 +129,7 @@ or_level* or_level_create(const or_problem* P, const int32_t* ord) {
       }
       double cr[3] = {a2[1] * a3[2] - a2[2] * a3[1], a2[2] * a3[0] - a2[0] * a3[2], a2[0] * a3[1] - a2[1] * a3[0]};
       L->J[o + p] = a1[0] * cr[0] + a1[1] * cr[1] + a1[2] * cr[2];
-      for (int c = 0; c < 3; c++) L->X[c * nn + o + p] = X[c * npe + p];
+      for (int c = 0; c < 3; c++) L->X[c * nn + o + p] = X[c * npe + p] + x0[c];
       for (int q = 0; q < 9; q++) L->Ja[q * nn + o + p] = Ja[q * npe + p];
     }
     /* face metric: J a^d traced to face d+- with l(+-1); outward sign */

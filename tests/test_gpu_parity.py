@@ -217,3 +217,43 @@ def test_full_size_fas_fixed_point(ctx, which):
     n_evals = (nlev - 1) * 8 + 7 + 1
     ss, _ = state_scale(o, wl, n_evals)
     check(np_(Q1), wl.Q, ss, 1e-12, f"{which} FAS fixed point")
+
+
+def test_full_size_batch_bench_configuration(ctx):
+    """The headline workload at full size in the bench's launch configuration (64 problems, 63.9M DOF, mixed
+    precision, divergence guard, autotuned tiles and launch classes, graph replay): the batched fine-level
+    residual of sampled problems (the smallest, the median-sized and the largest) against the oracle, entry by
+    entry, and the FAS fixed point of one batched V-cycle through the FP32 levels (S = A(Q): every level's FAS
+    problem is solved, so the cycle leaves each problem's state unchanged up to its round-off)."""
+    from oracle import oracle as O
+    from paper_1806_11456_amd import pmg
+    wls = I.config_batch()
+    meshes = [pmg.Mesh(ctx, w.mesh) for w in wls]
+    b = pmg.Batch(ctx, meshes, [w.orders for w in wls], [w.phys for w in wls],
+                  pmg.MG(beta_pre=2, beta_post=2, beta_coarse=4, precision=1, guard=8))
+    Q = b.tensor(np.concatenate([w.Q for w in wls], axis=1))
+    b.autotune()
+    b.set_graph(True)
+    print("[parity] batch tiles:", [b.level_tile_choice(-1, l) for l in range(b.level_info(-1))], flush=True)
+    R = b.residual(Q)
+    sizes = np.array([w.n_nodes for w in wls])
+    order = np.argsort(sizes, kind="stable")
+    sample = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    S = -R  # R = 0 - A(Q): S = A(Q)
+    Q1 = Q.clone()
+    b.vcycle(Q1, S, n_cycles=1)
+    nlev = b.level_info(-1)
+    # per level above the coarsest: 2 + 2 sweeps of 3 stages, the FAS source and the restricted residual; on the
+    # coarsest 4 sweeps of 3 stages and its source; the residual that formed S
+    n_evals = (nlev - 1) * 14 + 13 + 1
+    exact = 0
+    for p in sample:
+        w = wls[p]
+        o = O.Oracle(w.mesh, w.phys)
+        A, scale = o.operator_scale(w.orders, w.Q)
+        check(np_(b.part(R, p)), -A, scale, 1e-12, f"batch problem {p} ({w.n_nodes} nodes) residual")
+        ss, _ = state_scale(o, w, n_evals)
+        q1 = np_(b.part(Q1, p))
+        exact += int(np.array_equal(q1, w.Q))
+        check(q1, w.Q, ss, 1e-12, f"batch problem {p} FAS fixed point")
+    print(f"[parity] batch FAS fixed point bitwise in {exact} of {len(sample)} sampled problems")
