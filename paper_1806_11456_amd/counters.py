@@ -24,13 +24,17 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+RESIDUAL_SOURCES = ("device.h", "kernels_elem.inc", "kernels_face.inc")
+
+
 def source_hash() -> str:
-    """SHA-256 over the device sources: the kernels (kernels_*.inc) and their device helpers (device.h).  The
-    host library (launch sizes, drivers) is not hashed."""
+    """SHA-256 over the device sources of the residual's kernels (element and face kernels and their device
+    helpers): what the counted traffic depends on.  Setup, transfer and reduction kernels and the host
+    library (launch sizes, drivers) are not hashed."""
     h = hashlib.sha256()
     for path in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
         base = os.path.basename(path)
-        if not (base == "device.h" or (base.startswith("kernels_") and base.endswith(".inc"))):
+        if base not in RESIDUAL_SOURCES:
             continue
         with open(path, "rb") as f:
             h.update(os.path.basename(path).encode())
