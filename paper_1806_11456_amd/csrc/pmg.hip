@@ -2153,17 +2153,21 @@ pmg_status pmg_solve(pmg_solver s, double* Q_dev, const double* S_dev, double to
     ms.f32 = mixed;
     s->history.clear();
     DivGuard dg(s, st);
-    const std::vector<int> one(1, 1);
+    const std::vector<int> all(s->nprob, 1);  // a batch handle: every problem advances with the others
     for (;;) {
       residual(s, *s->top, (const double*)Q_dev, S_dev, s->d_R, false, SLOT_NORM, st);
-      r = read_slot(s, SLOT_NORM, st);
-      std::vector<double> rv(1, r);
-      if (!dg.check(rv, one, Q_dev).empty()) throw PmgError(PMG_ERR_NONPHYSICAL, "diverged after every step halving");
-      r = rv[0];
+      std::vector<double> rv = read_slots(s, SLOT_NORM, st);  // per problem
+      if (!dg.check(rv, all, Q_dev).empty()) throw PmgError(PMG_ERR_NONPHYSICAL, "diverged after every step halving");
+      r = 0.0;
+      bool rolled = false;
+      for (int p = 0; p < s->nprob; p++) {
+        r = (rv[p] > r || rv[p] != rv[p]) ? rv[p] : r;  // max over problems, NaN wins
+        rolled = rolled || dg.rolled[p];
+      }
       s->history.push_back(r);
       if (r != r) throw PmgError(PMG_ERR_NONPHYSICAL, "non-finite residual");
       if (r < tol || cycles >= max_cycles) break;
-      if (dg.rolled[0]) ms.rolled_back();
+      if (rolled) ms.rolled_back();
       else ms.update(r, patience);
       if (s->mg.tuning) {
         // residual-based tuning reads norms inside the cycle: eager launches

@@ -89,3 +89,26 @@ def test_guard_gives_up_and_freezes(ctx):
         cs, rs = s.solve(Qs, None, tol=1e-30, max_cycles=12, raise_not_converged=False)
         assert cs == cyc[p] and rs == r[p]
         assert np.array_equal(np_(b2.part(Q2, p)), np_(Qs)), p
+
+
+def test_guard_in_solve_on_batch_handle(ctx):
+    """pmg_solve on a batch handle (every problem advanced by every cycle, stopping on the largest residual)
+    guards each problem with its own residual: the unstable problem is restored and halved as in the batched
+    driver, and with no problem converging both drivers run the same cycles, so the states agree bitwise."""
+    from paper_1806_11456_amd import pmg
+    probs = _problems()
+    meshes = [pmg.Mesh(ctx, w.mesh) for w in probs]
+    res = []
+    for driver in ("solve", "solve_all"):
+        b = pmg.Batch(ctx, meshes, [w.orders for w in probs], [w.phys for w in probs], pmg.MG(guard=6, **MG))
+        Q = b.tensor(np.concatenate([w.Q for w in probs], axis=1))
+        if driver == "solve":
+            cyc, r = b.solve(Q, None, tol=1e-30, max_cycles=6, raise_not_converged=False)
+        else:
+            cyc, r = b.solve_all(Q, None, tol=1e-30, max_cycles=6, raise_not_converged=False)
+        halv, _ = b.guard_stats()
+        print(driver, cyc, r, halv)
+        res.append((np_(Q), halv))
+    assert res[0][1][1] > 0 and res[0][1][0] == 0 and res[0][1][2] == 0
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][0], res[1][0])
