@@ -143,12 +143,13 @@ def sq_summary(dirs, R, title, command, alg_flops):
         lines.append(f"| {k} | {w:.0f} | {frac('SQ_WAIT_ANY'):.2f} | {frac('SQ_ACTIVE_INST_VALU'):.2f} | "
                      f"{frac('SQ_ACTIVE_INST_LDS'):.2f} | {per('SQ_INSTS_VALU'):.0f} | {per('SQ_INSTS_LDS'):.0f} | "
                      f"{per('SQ_INSTS_VMEM_RD'):.0f} | {fl / 1e9:.3f} | {g(k, 'SQ_INSTS_VALU_MFMA_F64'):.0f} |")
-    lines += ["", f"FP64 VALU flops per residual as counted {tot_fl / 1e9:.3f} GFLOP (counter x 64 lanes) against the "
-                  f"surveyed model's {alg_flops / 1e9:.3f} GFLOP.  The SQ counters are collected per shader engine and "
-                  "the wave counts here are a fraction (1/5 to 1/10) of the waves the launches create, so absolute "
-                  "counts (waves, flops) are not compared; the ratios within a kernel (time waiting, VALU and LDS "
-                  "issue, instructions per wave) are.  No FP64 MFMA instruction runs: the contractions use the FP64 "
-                  "vector units, which are busy 6-17 % of the wave time, so matrix cores would not shorten them."]
+    lines += ["", f"FP64 VALU flops per residual as counted {tot_fl / 1e9:.3f} GFLOP (counter x 64: every lane of each "
+                  f"FP64 VALU instruction, masked lanes included, an upper bound) against the surveyed model's "
+                  f"{alg_flops / 1e9:.3f} GFLOP.  Counts are summed over the shader engines the profiler read; other "
+                  "runs of the same command have read a subset of them (1/5 to 1/10 of the waves), so absolute counts "
+                  "are not compared across runs; the ratios within a kernel (time waiting, VALU and LDS issue, "
+                  "instructions per wave) are.  No FP64 MFMA instruction runs: the contractions use the FP64 vector "
+                  "units, which issue in a small fraction of the wave time, so matrix cores would not shorten them."]
     return "\n".join(lines) + "\n"
 
 
