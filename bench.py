@@ -328,7 +328,7 @@ def plate_line(args) -> dict:
 
 
 def serve_bench(args) -> dict:
-    """Served stream (configuration 5 recipe, reduced sizes): Poisson arrivals at 20/s of steady-solve
+    """Served stream (reduced sizes): Poisson arrivals at 20/s of steady-solve
     requests on random stretched boxes with a wall, solved to ||r||_inf < 1e-9 by the continuous-batching
     server, per-request solvers on several streams and union solvers (batched); baseline: the same list
     solved one after another with pmg_solve (plain FP64) on the same GPU, queued first come, first served at

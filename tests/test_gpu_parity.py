@@ -1,8 +1,8 @@
 """GPU parity: every C-ABI entry point against the CPU oracle on the same seeded inputs (FP64, 1e-12 scaled).
 
 Small cases span several tiles and ragged tails, every orientation code, mortars between all order
-pairs 1..7, walls, far field and self-periodic faces; the full-size flat plate (configuration 2) and
-anisotropic O-grid (configuration 3) residuals are compared entry by entry.
+pairs 1..7, walls, far field and self-periodic faces; the full-size flat plate (64x32x1, N=(6,6,1)) and
+anisotropic O-grid (4,992 hexes, orders 1..7) residuals are compared entry by entry.
 """
 import numpy as np
 import pytest
@@ -156,7 +156,7 @@ def test_solve_fmg_tuning(ctx, pairs):
 
 @pytest.mark.parametrize("which", ["plate", "ogrid"])
 def test_full_size_residual(ctx, which):
-    """Configuration 2 (64x32x1 plate, N=(6,6,1)) and 3 (4992-hex O-grid, orders 1..7): every entry."""
+    """The 64x32x1 plate with N=(6,6,1) and the 4992-hex O-grid with orders 1..7 at full size: every entry."""
     from oracle import oracle as O
     from paper_1806_11456_amd import pmg
     wl = I.config_plate() if which == "plate" else I.config_ogrid()
@@ -198,7 +198,7 @@ def test_full_size_bench_step(ctx):
 
 @pytest.mark.parametrize("which", ["plate", "ogrid"])
 def test_full_size_fas_fixed_point(ctx, which):
-    """Configurations 2 and 3 at full size (the O-grid's random orders 1..7 include 8-node elements): with the
+    """The plate and the O-grid at full size (the O-grid's random orders 1..7 include 8-node elements): with the
     source S = A(Q) every level's FAS problem is already solved, so one V-cycle leaves Q unchanged up to the
     round-off its operator evaluations carry (a property that holds at any size; the oracle gives the scales)."""
     from oracle import oracle as O
