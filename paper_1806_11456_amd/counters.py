@@ -180,9 +180,61 @@ def kernel_stats(path, title, command):
     return "\n".join(lines) + "\n"
 
 
+def step_breakdown(path: str, marker: str, title: str, command: str) -> str:
+    """One solver step from a --kernel-trace run: in the run's longest stretch of GPU work, the dispatches
+    between the last two dispatches of 'marker' before the final one (a kernel launched once per step, e.g. the
+    restriction out of the finest level), summed per kernel and launch size (workgroups), so that each level
+    of the hierarchy shows as its own rows."""
+    found = glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True)
+    if not found:
+        raise SystemExit(f"no kernel_trace.csv under {path}")
+    rows = []
+    with open(found[0], newline="") as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"],
+                         int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))))
+    rows.sort()
+    # the run's longest stretch of GPU work (dispatches closer than 20 ms apart): the workload of interest when
+    # several run one after another
+    segs, cur = [], [rows[0]]
+    for r in rows[1:]:
+        if r[0] - cur[-1][1] > 20_000_000:
+            segs.append(cur)
+            cur = [r]
+        else:
+            cur.append(r)
+    segs.append(cur)
+    rows = max(segs, key=lambda sg: sum(t1 - t0 for t0, t1, _, _ in sg))
+    marks = [i for i, r in enumerate(rows) if r[2].replace("void ", "").startswith(marker)]
+    if len(marks) < 3:
+        raise SystemExit(f"fewer than 3 dispatches of {marker}")
+    a, b = marks[-3], marks[-2]
+    step = rows[a:b]
+    agg = {}
+    for t0, t1, name, wg in step:
+        key = (name.replace("void ", "").split("(")[0], wg)
+        n, t = agg.get(key, (0, 0.0))
+        agg[key] = (n + 1, t + (t1 - t0) * 1e-6)
+    busy = sum(v[1] for v in agg.values())
+    span = (step[-1][1] - step[0][0]) * 1e-6
+    lines = [f"# One solver step by kernel and launch size: {title}", "", "Command (repository root, TMPDIR=/tmp, "
+             "one MI355X):", "", f"    {command}", "",
+             f"The dispatches from one '{marker}' launch to the next (one step), {len(step)} dispatches, "
+             f"{busy:.1f} ms of kernel time in a {span:.1f} ms span.  Launch sizes tell the levels apart "
+             "(element-tile kernels: one workgroup per tile; face kernels: one per face tile).", "",
+             "| kernel | workgroups | launches | ms | us per launch |", "|---|---|---|---|---|"]
+    for (name, wg), (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        if t < 0.05 * busy / 100:
+            continue
+        lines.append(f"| {name} | {wg} | {n} | {t:.2f} | {1e3 * t / n:.1f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", default=None, help="summarise a --kernel-trace output directory")
+    ap.add_argument("--step", default=None, help="one solver step of a --kernel-trace output directory")
+    ap.add_argument("--marker", default="k_transfer<double, float, 10>", help="--step: a kernel launched once per step")
     ap.add_argument("--sq", nargs="+", default=None, help="SQ counter pass directories to summarise per residual")
     ap.add_argument("--alg-flops", type=float, default=0.0)
     ap.add_argument("--title", default="")
@@ -200,6 +252,12 @@ def main() -> int:
     args = ap.parse_args()
     if args.sq:
         txt = sq_summary(args.sq, args.residual or 10, args.title, args.command, args.alg_flops)
+        with open(args.out, "w") as f:
+            f.write(txt)
+        print(txt)
+        return 0
+    if args.step:
+        txt = step_breakdown(args.step, args.marker, args.title, args.command)
         with open(args.out, "w") as f:
             f.write(txt)
         print(txt)
