@@ -229,18 +229,47 @@ def batch_line(args, wls) -> dict:
     dofs = np.diff(b.problem_offsets).astype(np.float64)
     done = float(np.sum(dofs * per_cycle * cyc) + b.n_nodes * (args.steps + 1))
     fp32 = b.fp32_cycles()
+    tiles = tile_desc(b)
+    n_nodes = b.n_nodes
+    fp64 = None
+    if not args.no_batch_fp64:
+        # the same calls on an FP64 batch from the same start: the mixed precision's saving and its state error
+        Qm = Q.detach().cpu().numpy()
+        del b, Q
+        torch.cuda.synchronize()
+        b64 = pmg.Batch(ctx, meshes, [w.orders for w in wls], [w.phys for w in wls],
+                        pmg.MG(beta_pre=b1, beta_post=b2, beta_coarse=bc, precision=0, guard=8))
+        Q64 = b64.tensor(np.concatenate([w.Q for w in wls], axis=1))
+        b64.autotune()
+        b64.set_graph(True)
+        b64.solve_all(Q64, None, tol=0.0, max_cycles=args.warmup, raise_not_converged=False, raise_failed=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b64.solve_all(Q64, None, tol=0.0, max_cycles=args.steps, raise_not_converged=False, raise_failed=False)
+        torch.cuda.synchronize()
+        wall64 = time.perf_counter() - t0
+        h64, _ = b64.guard_stats()
+        Qd = Q64.detach().cpu().numpy()
+        err = np.abs(Qm - Qd).max(axis=1) / np.abs(Qd).max(axis=1)
+        fp64 = {"ms_per_step": 1e3 * wall64 / args.steps, "mixed_speedup": wall64 / wall,
+                "guard_halvings": int(h64.sum()), "state_error_of_mixed": [float(x) for x in err],
+                "state_error_meaning": "after the same warm-up and timed steps from the same start: "
+                                       "max |Q_mixed - Q_fp64| / max |Q_fp64| per variable over the batch"}
+        print(f"batch FP64: {fp64['ms_per_step']:.1f} ms/step, mixed {fp64['mixed_speedup']:.2f}x faster, state "
+              f"error {np.array2string(err, precision=2)}", file=sys.stderr, flush=True)
+        del b64, Q64
     return {"value": done / wall, "ms_per_step": 1e3 * wall / args.steps,
             "config": {"workload": "64 independent steady problems (seed 4): random boxes of 2k..20k hexes "
                                    "stretched toward a no-slip wall, orders iid U{2..5}^3, Mach U[0.1,0.4], "
                                    "Re U[1e2,1e4], trilinear mapping, Gauss nodes",
-                       "dof": b.n_nodes, "problems": len(wls),
+                       "dof": n_nodes, "problems": len(wls),
                        "step": f"batched solve-driver iteration: FP64 residual check + divergence guard + one FAS "
                                f"V-cycle (levels 5..1, beta {b1}/{b2}/{bc}), FP32 coarse levels, graph replay",
-                       "tiles": tile_desc(b), "fine_residual_evals_per_step": per_cycle + 1,
+                       "tiles": tiles, "fine_residual_evals_per_step": per_cycle + 1,
                        "setup_s": round(setup, 2)},
             "guard_halvings": int(halv.sum()), "problems_halved": int((halv > 0).sum()),
             "problems_given_up": int(np.isnan(r).sum()), "cycles_run": int(np.sum(cyc)),
-            "fp32_cycles_min": int(fp32.min()), "residual_max": float(np.nanmax(r)), **roof}
+            "fp32_cycles_min": int(fp32.min()), "residual_max": float(np.nanmax(r)), "fp64": fp64, **roof}
 
 
 def ogrid_line(args) -> dict:
@@ -926,6 +955,7 @@ def main() -> int:
     ap.add_argument("--cpu-single-s", type=float, default=12.0)
     ap.add_argument("--cpu-rounds", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch-fp64", action="store_true", help="skip the FP64 run of the batch beside the mixed one")
     ap.add_argument("--serve", action="store_true", help="served-stream latency benchmark instead of the plate")
     ap.add_argument("--serve-n", type=int, default=24)
     ap.add_argument("--serve-kmin", type=int, default=64)
@@ -1048,7 +1078,7 @@ def main() -> int:
         "lines": {k: v for k, v in results.items() if k != head},
     }
     for k in ("guard_halvings", "problems_halved", "problems_given_up", "cycles_run", "fp32_cycles_min",
-              "residual_max", "mixed"):
+              "residual_max", "mixed", "fp64"):
         if k in h:
             out[k] = h[k]
     if cpu is not None:
