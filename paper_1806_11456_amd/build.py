@@ -23,6 +23,24 @@ FLAGS = [
 ]
 
 
+# The same library with the host code under AddressSanitizer (device code unchanged), for the CPU checks of
+# its host-side logic (order selection, functionals' host parts, argument checking); it is never loaded by the
+# GPU tests or the benchmark.
+ASAN_LIB = os.path.join(HERE, "libpmg_asan_host.so")
+ASAN_FLAGS = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_asan_host(verbose: bool = False) -> str:
+    tmp = ASAN_LIB + ".tmp"
+    flags = [f for f in FLAGS if f != "-O3"] + ASAN_FLAGS
+    cmd = [HIPCC, *flags, SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, ASAN_LIB)
+    return ASAN_LIB
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, SRC, "-o", tmp]

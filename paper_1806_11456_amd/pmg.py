@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpmg.so")
+# PMG_LIB names another build of the same library (the host-sanitizer build of the CPU checks); there is no
+# fallback when the file is missing
+LIB_PATH = os.environ.get("PMG_LIB") or os.path.join(HERE, "libpmg.so")
 
 STATUS = {0: "PMG_OK", 1: "PMG_ERR_INVALID_ARG", 2: "PMG_ERR_OOM", 3: "PMG_ERR_HIP", 4: "PMG_ERR_NONPHYSICAL",
           5: "PMG_ERR_NOT_CONVERGED", 6: "PMG_ERR_BUSY", 7: "PMG_ERR_UNIMPLEMENTED"}
