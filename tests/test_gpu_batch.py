@@ -211,3 +211,24 @@ def test_tile_choices_bitwise_ogrid(ctx):
         # unrecorded truncation-error entries are NaN on every choice
         for a, r, what in zip(out, ref, ("residual", "state after a V-cycle", "tau", "isolated tau")):
             assert np.array_equal(a, r, equal_nan=True), (target, split, what, float(np.nanmax(np.abs(a - r))))
+
+
+def test_determinism_run_twice(ctx, problems):
+    """The same calls from the same state give bitwise the same results, on the same solver and on a second
+    one built alike (no atomics in floating-point accumulations; reductions in a fixed order)."""
+    from paper_1806_11456_amd import pmg
+    meshes = [pmg.Mesh(ctx, w.mesh) for w in problems]
+    out = []
+    for run in range(3):
+        if run in (0, 2):  # runs 0 and 1 on one solver, run 2 on a second one
+            b = pmg.Batch(ctx, meshes, [w.orders for w in problems], [w.phys for w in problems],
+                          pmg.MG(precision=1, **MG))
+        Q = batch_state(b, problems)
+        R = np_(b.residual(Q))
+        b.vcycle(Q, None, n_cycles=2)
+        tau = np_(b.tau_estimate(Q.clone(), None, isolated=False))
+        out.append((R, np_(Q), tau, np.asarray(b.norms(Q))))
+        print(f"[determinism] run {run}", flush=True)
+    for run in (1, 2):
+        for a, r, what in zip(out[run], out[0], ("residual", "state", "tau map", "norms")):
+            assert np.array_equal(a, r, equal_nan=True), (run, what)
