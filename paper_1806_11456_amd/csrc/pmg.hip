@@ -998,10 +998,23 @@ static void timestep(const pmg_solver_s* s, Level& L, const T* Q, hipStream_t st
 
 template <class T>
 static void smooth(const pmg_solver_s* s, Level& L, T* Q, const T* S, T* G, int sweeps, hipStream_t st,
-                   const int* act = nullptr) {
+                   const int* act = nullptr, const T* R1 = nullptr) {
   for (int it = 0; it < sweeps; it++) {
     timestep(s, L, (const T*)Q, st, act);
     for (int k = 0; k < 3; k++) {
+      if (it == 0 && k == 0 && R1) {
+        // the first stage's residual at this state is R1 (formed with the coarse source from the same
+        // evaluation, bitwise what the stage's own evaluation would give): the update alone, then the traces
+        // of the new state, which the next stage's evaluation takes as its own
+        LevelDevT<T> D = L.devT<T>();
+        if (act) D.active = D.skip = act;
+        k_rk_first<T><<<cdiv(L.nn, 256), 256, 0, st>>>(D, R1, Q, G, RK_B[0]);
+        launch_trace(L, D, (const T*)Q, L.work<T>().qf, st);
+        s->qf_level = &L;
+        s->qf_src = (const void*)Q;
+        s->qf_act = act;
+        continue;
+      }
       DivArgs<T> a = div_args<T>(EPI_RK);
       a.S = S;
       a.Qrk = Q;
@@ -1027,9 +1040,9 @@ static void residual(const pmg_solver_s* s, Level& L, const T* Q, const T* S, T*
 
 // The same on buffers held in the level's own precision.
 static void smooth_any(const pmg_solver_s* s, Level& L, void* Q, const void* S, void* G, int sweeps, hipStream_t st,
-                       const int* act = nullptr) {
-  if (L.prec == PREC_F32) smooth(s, L, (float*)Q, (const float*)S, (float*)G, sweeps, st, act);
-  else smooth(s, L, (double*)Q, (const double*)S, (double*)G, sweeps, st, act);
+                       const int* act = nullptr, const void* R1 = nullptr) {
+  if (L.prec == PREC_F32) smooth(s, L, (float*)Q, (const float*)S, (float*)G, sweeps, st, act, (const float*)R1);
+  else smooth(s, L, (double*)Q, (const double*)S, (double*)G, sweeps, st, act, (const double*)R1);
 }
 
 static void residual_any(const pmg_solver_s* s, Level& L, const void* Q, const void* S, void* out, bool isolated,
@@ -1257,12 +1270,14 @@ static double pre_smooth(CycleCtx& c, int l, int top) {
   Hier& H = *c.H;
   Level& L = *H.lv[l];
   const pmg_mg_params& P = s->mg;
+  // below the top, the coarse source left the first stage's residual in R[l] (not with tuning)
+  const void* R1 = (l < top && !P.tuning) ? H.R[l] : nullptr;
   if (l == 0) {
-    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_coarse, c.st, c.act);
+    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_coarse, c.st, c.act, R1);
     return 0.0;
   }
   if (!P.tuning) {
-    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_pre, c.st, c.act);
+    smooth_any(s, L, H.Q[l], H.S[l], H.G[l], P.beta_pre, c.st, c.act, R1);
     residual_any(s, L, H.Q[l], H.S[l], H.R[l], false, -1, c.st, c.act);
     return 0.0;
   }
@@ -1308,6 +1323,7 @@ static void coarse_source(CycleCtx& c, int l) {
   DivArgs<T> a = div_args<T>(EPI_SRC);
   a.S = (const T*)H.r[l];
   a.out = (T*)H.S[l];
+  if (!s->mg.tuning) a.out2 = (T*)H.R[l];  // the first pre-smoothing stage's residual (pre_smooth)
   const bool rec = c.tau != nullptr;
   T* nodal = nullptr;
   if (rec && c.tau->nodal && H.dir == c.tau->nodal_dir && H.caps[l] == c.tau->nodal_cap) {
