@@ -181,7 +181,8 @@ def kernel_stats(path, title, command):
 
 
 def step_breakdown(path: str, marker: str, title: str, command: str) -> str:
-    """One solver step from a --kernel-trace run: in the run's longest stretch of GPU work, the dispatches
+    """One solver step from a --kernel-trace run: in the run's longest stretch of GPU work with at least three
+    dispatches of 'marker', the dispatches
     between the last two dispatches of 'marker' before the final one (a kernel launched once per step, e.g. the
     restriction out of the finest level), summed per kernel and launch size (workgroups), so that each level
     of the hierarchy shows as its own rows."""
@@ -204,8 +205,10 @@ def step_breakdown(path: str, marker: str, title: str, command: str) -> str:
         else:
             cur.append(r)
     segs.append(cur)
+    is_mark = lambda r: r[2].replace("void ", "").startswith(marker)
+    segs = [sg for sg in segs if sum(1 for r in sg if is_mark(r)) >= 3] or segs
     rows = max(segs, key=lambda sg: sum(t1 - t0 for t0, t1, _, _ in sg))
-    marks = [i for i, r in enumerate(rows) if r[2].replace("void ", "").startswith(marker)]
+    marks = [i for i, r in enumerate(rows) if is_mark(r)]
     if len(marks) < 3:
         raise SystemExit(f"fewer than 3 dispatches of {marker}")
     a, b = marks[-3], marks[-2]
