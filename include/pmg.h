@@ -327,7 +327,7 @@ pmg_status pmg_solve_stats(pmg_solver s, int32_t* fp32_cycles);
  * from the host (only for fixed sweep counts).  Results are identical to the eager launches.
  */
 pmg_status pmg_set_graph(pmg_solver s, int enable);
-/* Tile autotuner: times the operator on every built level for element tiles of about 64, 128, 256 and 512
+/* Tile autotuner: times the operator on every built level for element tiles of about 32, 64, 128, 256 and 512
  * nodes and, for each, the gradient and the divergence kernels launched either as one grid over every tile
  * or once per class of tiles by size (at most 64, 128, 256 nodes, larger) with a block size per class (split
  * bit 0: gradient, bit 1: divergence), and keeps the fastest (cached per context by the level's order-bucket
@@ -335,7 +335,7 @@ pmg_status pmg_set_graph(pmg_solver s, int enable);
  * (split, nullable) its split bits. */
 pmg_status pmg_autotune(pmg_solver s, void* stream);
 pmg_status pmg_level_tiles(pmg_solver s, int hierarchy, int level, int32_t* tile_target, int32_t* split);
-/* Sets one level's element tiles by hand (tile_target 64, 128, 256 or 512 nodes; split 0..3, as above):
+/* Sets one level's element tiles by hand (tile_target 32, 64, 128, 256 or 512 nodes; split 0..3, as above):
  * waits for the device, rebuilds the level's tile arrays and drops the solver's captured graphs.  Results do
  * not change.  PMG_ERR_INVALID_ARG for other values or a level out of range. */
 pmg_status pmg_set_tiles(pmg_solver s, int hierarchy, int level, int tile_target, int split);

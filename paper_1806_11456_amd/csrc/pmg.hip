@@ -1155,8 +1155,8 @@ static void autotune_level(pmg_solver_s* s, Level& L, hipStream_t st) {
   s->prof->mask = 0;
   int best = L.tile_target, best_split = L.tile_split;
   float best_t = 1e30f;
-  for (int cand = 0; cand < 16; cand++) {
-    const int target = 64 << (cand >> 2), split = cand & 3;
+  for (int cand = 0; cand < 20; cand++) {
+    const int target = 32 << (cand >> 2), split = cand & 3;
     build_tiles(s, L, target, split);
     if (split) {
       int used = 0;
@@ -1976,8 +1976,8 @@ pmg_status pmg_autotune(pmg_solver s, void* stream) {
 pmg_status pmg_set_tiles(pmg_solver s, int hierarchy, int level, int tile_target, int split) {
   return guard([&] {
     REQUIRE(s, "NULL solver");
-    REQUIRE(tile_target == 64 || tile_target == 128 || tile_target == 256 || tile_target == 512,
-            "tile_target must be 64, 128, 256 or 512");
+    REQUIRE(tile_target == 32 || tile_target == 64 || tile_target == 128 || tile_target == 256 || tile_target == 512,
+            "tile_target must be 32, 64, 128, 256 or 512");
     REQUIRE(split >= 0 && split <= 3, "split must be 0..3");
     Hier& H = pick_hier(s, hierarchy);
     REQUIRE(level >= 0 && level < (int)H.lv.size(), "level out of range");

@@ -523,7 +523,7 @@ class Solver:
         _check(lib().pmg_autotune(self.h, _stream()))
 
     def level_tiles(self, hierarchy: int, level: int) -> int:
-        """The level's element-tile node target (64, 128, 256 or 512)."""
+        """The level's element-tile node target (32, 64, 128, 256 or 512)."""
         return self.level_tile_choice(hierarchy, level)[0]
 
     def set_tiles(self, hierarchy: int, level: int, target: int, split: int = 0):

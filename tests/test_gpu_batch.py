@@ -147,7 +147,7 @@ def test_autotune_keeps_results(ctx, problems):
     R0 = np_(s.residual(s.tensor(w.Q)))
     s.autotune()
     for l in range(s.level_info(-1)):
-        assert s.level_tiles(-1, l) in (64, 128, 256, 512)
+        assert s.level_tiles(-1, l) in (32, 64, 128, 256, 512)
     R1 = np_(s.residual(s.tensor(w.Q)))
     assert np.array_equal(R0, R1)
 
@@ -159,7 +159,7 @@ def _set_all_tiles(s, target, split, hierarchies=(-1,)):
             assert s.level_tile_choice(h, l) == (target, split)
 
 
-TILE_CHOICES = [(t, sp) for t in (64, 128, 256, 512) for sp in range(4)]
+TILE_CHOICES = [(t, sp) for t in (32, 64, 128, 256, 512) for sp in range(4)]
 
 
 def test_tile_choices_bitwise_batch(ctx, problems):
