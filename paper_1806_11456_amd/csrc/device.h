@@ -10,7 +10,8 @@
 #define PMG_MAXN 8        // nodes per direction (order <= 7)
 #define PMG_BLOCK 256     // threads per element / face tile
 #define PMG_TILE_MAX 512  // nodes per element tile (one element of 8x8x8)
-#define PMG_NPT 2         // nodes per thread = PMG_TILE_MAX / PMG_BLOCK
+#define PMG_NPT 2         // nodes per thread of a PMG_BLOCK block over a PMG_TILE_MAX tile (the library launches
+                          // PMG_TILE_MAX-thread blocks for such tiles instead)
 #define PMG_FACE_TILE 256 // mortar nodes per face tile
 #define PMG_MAX_TILE_ELEMS 64
 

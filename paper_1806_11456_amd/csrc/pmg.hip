@@ -160,8 +160,8 @@ static int grad_lds_words(int nodes, int face_nodes) { return 13 * nodes + 7 * f
 // LDS of the divergence kernel: the nodal fluxes, and Phi at the face nodes (or the updated state at the nodes).
 static int div_lds_words(int nodes, int face_nodes) { return 15 * nodes + 5 * std::max(nodes, face_nodes); }
 
-// A range of a level's element tiles launched with one block size: the smallest of 64, 128, 256 threads that
-// holds the range's largest tile, one node per thread unless a tile is larger than 256 nodes (npt 2).
+// A range of a level's element tiles launched with one block size: the smallest of 64, 128, 256, 512 threads
+// that holds the range's largest tile, one node per thread.
 struct TileClass {
   int first = 0, count = 0, block = PMG_BLOCK, npt = 1, max_tile = 1, grad_words = 1, div_words = 1;
 };
@@ -430,8 +430,8 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target, int split =
       }
     C.count = (int)order.size() - C.first;
     const int b = block_of(C.max_tile);
-    C.block = b == 0 ? 64 : (b == 1 ? 128 : PMG_BLOCK);
-    C.npt = b == 3 ? PMG_NPT : 1;
+    C.block = b == 0 ? 64 : (b == 1 ? 128 : (b == 2 ? PMG_BLOCK : PMG_TILE_MAX));
+    C.npt = 1;
   }
   std::vector<int4> otiles(tiles.size());
   for (size_t t = 0; t < order.size(); t++) otiles[t] = tiles[order[t]];
@@ -486,8 +486,8 @@ static void build_tiles(const pmg_solver_s* s, Level& L, int target, int split =
   A.grad_words = grad_words;
   A.div_words = div_words;
   const int ba = block_of(max_tile);
-  A.block = ba == 0 ? 64 : (ba == 1 ? 128 : PMG_BLOCK);
-  A.npt = ba == 3 ? PMG_NPT : 1;
+  A.block = ba == 0 ? 64 : (ba == 1 ? 128 : (ba == 2 ? PMG_BLOCK : PMG_TILE_MAX));
+  A.npt = 1;
   L.all = A;
   L.dev.tiles = L.dev32.tiles = L.d_tiles;
   L.dev.elist = L.dev32.elist = L.d_elist;
@@ -833,7 +833,8 @@ static void launch_trace(const Level& L, const LevelDevT<T>& D, const T* Q, T* q
     const size_t lds = L.lds_trace(c);
     if (c.block == 64) k_trace<T, 64><<<c.count, 64, lds, st>>>(Dc, Q, qf);
     else if (c.block == 128) k_trace<T, 128><<<c.count, 128, lds, st>>>(Dc, Q, qf);
-    else k_trace<T, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, qf);
+    else if (c.block == PMG_BLOCK) k_trace<T, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, qf);
+    else k_trace<T, PMG_TILE_MAX><<<c.count, PMG_TILE_MAX, lds, st>>>(Dc, Q, qf);
   }
 }
 
@@ -847,9 +848,9 @@ static void launch_grad(const Level& L, const LevelDevT<T>& D, const T* Q, const
     if (c.block == 64) k_grad<T, 1, 64><<<c.count, 64, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
     else if (c.block == 128)
       k_grad<T, 1, 128><<<c.count, 128, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
-    else if (c.npt == 1)
+    else if (c.block == PMG_BLOCK)
       k_grad<T, 1, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
-    else k_grad<T, PMG_NPT, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
+    else k_grad<T, 1, PMG_TILE_MAX><<<c.count, PMG_TILE_MAX, lds, st>>>(Dc, Q, qf, Ws, isolated, gW, gf, fvn, phi);
   }
 }
 
@@ -864,8 +865,8 @@ static void launch_div(const Level& L, const LevelDevT<T>& D, const T* Q, const 
     const size_t lds = L.lds_div(c);
     if (c.block == 64) k_div<T, 1, 64><<<c.count, 64, lds, st>>>(Dc, Q, gW, Phi, ac);
     else if (c.block == 128) k_div<T, 1, 128><<<c.count, 128, lds, st>>>(Dc, Q, gW, Phi, ac);
-    else if (c.npt == 1) k_div<T, 1, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, gW, Phi, ac);
-    else k_div<T, PMG_NPT, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, gW, Phi, ac);
+    else if (c.block == PMG_BLOCK) k_div<T, 1, PMG_BLOCK><<<c.count, PMG_BLOCK, lds, st>>>(Dc, Q, gW, Phi, ac);
+    else k_div<T, 1, PMG_TILE_MAX><<<c.count, PMG_TILE_MAX, lds, st>>>(Dc, Q, gW, Phi, ac);
   }
 }
 
@@ -876,7 +877,8 @@ static void launch_dt(const Level& L, const LevelDevT<T>& D, const T* Q, unsigne
     const LevelDevT<T> Dc = class_dev(D, c);
     if (c.block == 64) k_dt<T, 64><<<c.count, 64, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
     else if (c.block == 128) k_dt<T, 128><<<c.count, 128, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
-    else k_dt<T, PMG_BLOCK><<<c.count, PMG_BLOCK, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
+    else if (c.block == PMG_BLOCK) k_dt<T, PMG_BLOCK><<<c.count, PMG_BLOCK, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
+    else k_dt<T, PMG_TILE_MAX><<<c.count, PMG_TILE_MAX, 0, st>>>(Dc, Q, L.d_hfac, out + c.first);
   }
 }
 

@@ -186,7 +186,7 @@ def test_tile_choices_bitwise_batch(ctx, problems):
 
 
 def test_tile_choices_bitwise_ogrid(ctx):
-    """The same on an O-grid with orders 1..7 (tiles up to 512 nodes: two nodes per thread), including the
+    """The same on an O-grid with orders 1..7 (tiles up to 512 nodes: 512-thread blocks), including the
     truncation-error estimate of the anisotropic hierarchies."""
     from paper_1806_11456_amd import pmg
     w = I.config_ogrid(nt=2, nr=3, r_out=3.0, ratio=1.2)
